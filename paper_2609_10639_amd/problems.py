@@ -1,0 +1,234 @@
+"""Seeded synthetic inputs for the VLBM hot path.
+
+This module only builds initial conditions: primitive states of the paper's
+benchmark families, converted to the conserved vector W = (rho, rho u, rho E)
+(Sec. II.A, Eqs. 1-2) through the caloric relation e(rho, P) of the chosen EOS,
+plus a counter-based random number generator.  It holds none of the method's
+arithmetic (no flux, equilibrium, sensor or time step) and both the CPU oracle
+and the GPU library consume the arrays it returns unchanged.
+
+Arrays are float64, shape (D+2, ny, nx) with ny == 1 in 1-D, cell centres at
+x_j = (j + 1/2) dx.
+"""
+import math
+
+import numpy as np
+
+# --------------------------------------------------------------- RNG
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed, idx):
+    """Counter-based SplitMix64 (Steele, Lea & Flood 2014): the (idx+1)-th
+    output of the generator seeded with `seed`, for an array of counters."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (idx + np.uint64(1)) * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform(seed, n):
+    """n uniforms in [0, 1): top 53 bits of SplitMix64 times 2^-53."""
+    z = splitmix64(seed, np.arange(n, dtype=np.uint64))
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def gaussian(seed, n):
+    """n standard normals by Box-Muller on the uniform pairs (2m, 2m+1)."""
+    m = (n + 1) // 2
+    u = uniform(seed, 2 * m)
+    u1, u2 = u[0::2], u[1::2]
+    r = np.sqrt(-2.0 * np.log1p(-u1))
+    z = np.concatenate([r * np.cos(2 * np.pi * u2), r * np.sin(2 * np.pi * u2)])
+    out = np.empty(2 * m)
+    out[0::2] = z[:m]
+    out[1::2] = z[m:]
+    return out[:n]
+
+
+# --------------------------------------------------------------- EOS parameters
+
+IDEAL, VDW = 0, 1
+
+
+class Gas:
+    """EOS parameters.  Ideal gas: gamma.  van der Waals: a, b, R and gamma with
+    c_v = R/(gamma - 1) (Sec. II.C)."""
+
+    def __init__(self, eos=IDEAL, gamma=1.4, a=0.0, b=0.0, R=1.0):
+        self.eos, self.gamma, self.a, self.b, self.R = eos, gamma, a, b, R
+
+    @property
+    def cv(self):
+        return self.R / (self.gamma - 1.0)
+
+    def internal_energy(self, rho, P):
+        """Specific internal energy e(rho, P): ideal P/((gamma-1) rho);
+        vdW T = (P + a rho^2)(1 - b rho)/(R rho), e = c_v T - a rho (Eqs. 16-17)."""
+        rho = np.asarray(rho, dtype=np.float64)
+        P = np.asarray(P, dtype=np.float64)
+        if self.eos == IDEAL:
+            return P / ((self.gamma - 1.0) * rho)
+        T = (P + self.a * rho * rho) * (1.0 - self.b * rho) / (self.R * rho)
+        return self.cv * T - self.a * rho
+
+    def config(self):
+        return dict(eos=self.eos, gamma=self.gamma, vdw_a=self.a, vdw_b=self.b, vdw_R=self.R)
+
+
+IDEAL_AIR = Gas(IDEAL, 1.4)
+# reduced van der Waals units rho_c = P_c = 1 (a = 3, b = 1/3, R = 1), c_v/R = 50
+VDW_REDUCED_CV50 = Gas(VDW, 1.0 + 1.0 / 50.0, 3.0, 1.0 / 3.0, 1.0)
+
+
+def conserved(gas, rho, u, P, v=None):
+    """(rho, u[, v], P) -> W = (rho, rho u[, rho v], rho E), E = e + |u|^2/2."""
+    rho = np.asarray(rho, dtype=np.float64)
+    e = gas.internal_energy(rho, P)
+    ke = 0.5 * u * u + (0.5 * v * v if v is not None else 0.0)
+    comps = [rho, rho * u] + ([rho * v] if v is not None else []) + [rho * (e + ke)]
+    return np.stack([np.broadcast_to(c, rho.shape) for c in comps]).astype(np.float64)
+
+
+def centres(n, lo, hi):
+    dx = (hi - lo) / n
+    return lo + (np.arange(n) + 0.5) * dx, dx
+
+
+# --------------------------------------------------------------- sensor settings
+
+# (beta_min, beta_max, C_sensor) of Sec. III.D.  1-D: the values the paper states
+# for its strong shock tube.  2-D: beta_min = 0.7, the largest constant beta
+# that keeps the all-shock four-quadrant problem admissible, and C = 16, the
+# smallest of 4, 8, 16 with which the sensor keeps it admissible.
+SENSOR_1D = dict(beta_min=0.75, beta_max=1.0, c_sensor=4.0)
+SENSOR_2D = dict(beta_min=0.7, beta_max=1.0, c_sensor=16.0)
+
+# --------------------------------------------------------------- 1-D problems
+
+
+def shock_tube(n, left, right, gas=IDEAL_AIR, x0=0.5, lo=0.0, hi=1.0):
+    """Riemann problem on [lo, hi]: (rho, u, P) = left for x < x0, right after."""
+    x, dx = centres(n, lo, hi)
+    L = x < x0
+    rho = np.where(L, left[0], right[0])
+    u = np.where(L, left[1], right[1])
+    P = np.where(L, left[2], right[2])
+    W = conserved(gas, rho, u, P)
+    return W.reshape(3, 1, n), dx
+
+
+def sod(n=1000):
+    """Sod tube: (1, 0, 1) | (0.125, 0, 0.1), ideal gamma = 1.4, [0, 1]."""
+    return shock_tube(n, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+
+
+# BZT tube states in reduced vdW units (c_v/R = 50): the paper's south-east and
+# north-east quadrant states of its BZT Riemann problem (Eq. 49, a = 1, b = 0.3),
+# converted by rho/rho_c, P/P_c, u/sqrt(P_c/rho_c) with rho_c = 1/(3b),
+# P_c = a/(27 b^2), the normal velocity taken along the tube.
+BZT_LEFT = (0.9, -0.25875, 1.005923)
+BZT_RIGHT = (0.585, 0.0, 0.893341)
+
+
+def bzt_tube(n=8192):
+    return shock_tube(n, BZT_LEFT, BZT_RIGHT, gas=VDW_REDUCED_CV50)
+
+
+# --------------------------------------------------------------- 2-D problems
+
+
+def isentropic_vortex_primitives(X, Y, t=0.0, L=10.0, strength=5.0, gamma=1.4,
+                                 centre=(5.0, 5.0), background=(1.0, 1.0)):
+    """Yee/Shu isentropic vortex advected by a uniform background flow.
+
+    Azimuthal speed u_phi = strength/(2 pi) r exp((1 - r^2)/2) (core radius 1),
+    closed by dP/dr = rho u_phi^2/r along the isentrope P = rho^gamma with
+    rho = P = 1 far away (Sec. IV.H): T = P/rho = 1 - (gamma-1) strength^2/(8 gamma pi^2)
+    exp(1 - r^2).  The centre at time t is centre + background*t, taken to the
+    nearest periodic image on [0, L)^2."""
+    cx = (centre[0] + background[0] * t) % L
+    cy = (centre[1] + background[1] * t) % L
+    dxp = (X - cx + 0.5 * L) % L - 0.5 * L
+    dyp = (Y - cy + 0.5 * L) % L - 0.5 * L
+    r2 = dxp * dxp + dyp * dyp
+    amp = strength / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+    u = background[0] - amp * dyp
+    v = background[1] + amp * dxp
+    T = 1.0 - (gamma - 1.0) * strength ** 2 / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = T ** (1.0 / (gamma - 1.0))
+    P = rho * T
+    return rho, u, v, P
+
+
+def vortex(n, L=10.0, strength=5.0, t=0.0):
+    """Periodic [0, L]^2 isentropic vortex, centre (5, 5), background (1, 1)."""
+    x, dx = centres(n, 0.0, L)
+    X, Y = np.meshgrid(x, x)
+    rho, u, v, P = isentropic_vortex_primitives(X, Y, t=t, L=L, strength=strength)
+    return conserved(IDEAL_AIR, rho, u, P, v), dx
+
+
+def vortex_perturbed(n, amplitude=1e-3, seed=42, L=10.0, strength=5.0):
+    """Vortex initial state plus amplitude * N(0, 1) on every component of W,
+    independent per cell and component (seeded SplitMix64 + Box-Muller)."""
+    W, dx = vortex(n, L, strength)
+    xi = gaussian(seed, W.size).reshape(W.shape)
+    return W + amplitude * xi, dx
+
+
+# Four-quadrant states (rho, u, v, P) of the paper's 2-D Riemann problems.
+RIEMANN_CONFIGS = {
+    12: dict(NE=(0.5313, 0.0, 0.0, 0.4), NW=(1.0, 0.7276, 0.0, 1.0),
+             SW=(0.8, 0.0, 0.0, 1.0), SE=(1.0, 0.0, 0.7276, 1.0)),
+    3: dict(NE=(1.5, 0.0, 0.0, 1.5), NW=(0.5323, 1.206, 0.0, 0.3),
+            SW=(0.138, 1.206, 1.206, 0.029), SE=(0.5323, 0.0, 1.206, 0.3)),
+}
+
+
+def riemann2d(n, config=3):
+    """Four-quadrant problem on [0, 1]^2, discontinuities along x = y = 1/2."""
+    x, dx = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x)
+    st = RIEMANN_CONFIGS[config]
+    rho = np.empty_like(X)
+    u = np.empty_like(X)
+    v = np.empty_like(X)
+    P = np.empty_like(X)
+    for q, mask in (("NE", (X > 0.5) & (Y > 0.5)), ("NW", (X < 0.5) & (Y > 0.5)),
+                    ("SW", (X < 0.5) & (Y < 0.5)), ("SE", (X > 0.5) & (Y < 0.5))):
+        rho[mask], u[mask], v[mask], P[mask] = st[q]
+    return conserved(IDEAL_AIR, rho, u, P, v), dx
+
+
+def bzt_extrusion(n=2048, noise=0.01, seed=1234):
+    """BZT tube extruded along y with rho *= 1 + noise (2U - 1), U seeded uniform,
+    velocity and pressure held (internal energy recomputed)."""
+    x, dx = centres(n, 0.0, 1.0)
+    X = np.broadcast_to(x[None, :], (n, n))
+    L = X < 0.5
+    rho = np.where(L, BZT_LEFT[0], BZT_RIGHT[0])
+    u = np.where(L, BZT_LEFT[1], BZT_RIGHT[1])
+    P = np.where(L, BZT_LEFT[2], BZT_RIGHT[2])
+    U = uniform(seed, n * n).reshape(n, n)
+    rho = rho * (1.0 + noise * (2.0 * U - 1.0))
+    return conserved(VDW_REDUCED_CV50, rho, u, P, np.zeros_like(rho)), dx
+
+
+def random_admissible_state(D, shape, seed, gas=IDEAL_AIR, rho_range=(0.5, 1.5),
+                            u_amp=0.5, P_range=(0.5, 1.5)):
+    """Smooth-free random admissible states for identity checks."""
+    n = int(np.prod(shape))
+    U = uniform(seed, (D + 2) * n).reshape(D + 2, *shape)
+    rho = rho_range[0] + (rho_range[1] - rho_range[0]) * U[0]
+    vel = [u_amp * (2 * U[1 + a] - 1) for a in range(D)]
+    P = P_range[0] + (P_range[1] - P_range[0]) * U[D + 1]
+    if D == 1:
+        return conserved(gas, rho, vel[0], P)
+    return conserved(gas, rho, vel[0], P, vel[1])
