@@ -1,0 +1,184 @@
+/*
+ * vlbm.h - C ABI of the MI355X (gfx950) vectorial lattice Boltzmann library.
+ *
+ * Method: Hosseini & Karlin, "Vectorial lattice Boltzmann solver for
+ * compressible inviscid flows with generic equation of state",
+ * arXiv 2609.10639.  One time step of the library is the paper's fused lattice
+ * update: moments W = sum_i f_i (Sec. III.A), EOS closure (Sec. II.C,
+ * Eqs. 13, 15-17), CFL retargeting of the link speed with exact moment
+ * reprojection (Sec. III.E, Eqs. 36-40), the Ducros-gated adaptive relaxation
+ * coefficient beta(x,t) (Sec. III.D, Eqs. 28-35), over-relaxation towards the
+ * flux-consistent vector equilibrium (Eqs. 20, 22), exact transport (Eq. 21)
+ * and the global max(|u_alpha| + c_s) reduction that feeds the next step.
+ *
+ * Conventions
+ *   - Lattices: D1Q2 (dim = 1) and D2Q4 (dim = 2).  Directions are ordered
+ *     (+x, -x, +y, -y); components (rho, rho u, [rho v,] rho E).
+ *   - Macroscopic arrays W are FP64, structure-of-arrays, shape
+ *     (dim+2, ny, nx), x fastest; ny == 1 in 1-D.  Cell centres at (j+1/2) dx.
+ *   - Populations live on the device in the precision chosen at creation
+ *     (FP64 or FP32): dim+2 component planes for each of the 2*dim directions,
+ *     plane index i*(dim+2)+k, each plane padded to `vlbm_plane_elems`.
+ *   - Every call is ordered on the HIP stream given in the config (NULL = the
+ *     default stream).  Calls that return host data synchronise that stream.
+ *   - Pointers flagged *_on_device are device pointers the caller owns; they
+ *     are only borrowed for the duration of the call (stream-ordered).
+ *   - Errors are returned as vlbm_status; no call aborts the process.  A
+ *     failing call leaves a message readable with vlbm_last_error().
+ *
+ * Readings of points the paper leaves open (identical in the CPU oracle):
+ *   - initial populations are the equilibrium at c0 = s_max(W0)/CFL;
+ *   - the final step of vlbm_run_to_time shortens dt to t_end - t, which is a
+ *     retarget to c = dx/(t_end - t) with reprojection; it triggers when
+ *     t + dt >= t_end (1 - 1e-14) and sets t = t_end exactly;
+ *   - a sensor normaliser max|Q_alpha,k| equal to 0 gives s_hat_k = 0;
+ *   - outflow is an edge-replicated ghost cell: streaming sources, central
+ *     differences and the box filter clamp their neighbour index;
+ *   - with retarget_every = K > 1 a retarget is forced when s_max > c.
+ */
+#ifndef VLBM_H
+#define VLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vlbm_ctx vlbm_ctx;
+
+typedef enum {
+    VLBM_OK = 0,
+    VLBM_EINVAL = -1,          /* invalid argument or configuration */
+    VLBM_ENOMEM = -2,          /* device allocation failed */
+    VLBM_EDEVICE = -3,         /* HIP runtime error */
+    VLBM_ENONHYPERBOLIC = -4,  /* rho <= 0, c_s^2 <= 0 or 1 - b rho <= 0 (Eq. 14) */
+    VLBM_ENONFINITE = -5       /* NaN or Inf in the state */
+} vlbm_status;
+
+enum { VLBM_BC_PERIODIC = 0, VLBM_BC_OUTFLOW = 1 };
+enum { VLBM_EOS_IDEAL = 0, VLBM_EOS_VDW = 1 };
+enum { VLBM_SENSOR_OFF = 0, VLBM_SENSOR_A = 1, VLBM_SENSOR_B = 2, VLBM_SENSOR_AUTO = 3 };
+enum { VLBM_FP64 = 0, VLBM_FP32 = 1 };
+
+/* Problem statement (Sec. II-III): lattice, grid, boundaries, EOS, time
+ * stepping and sensor constants. */
+typedef struct {
+    int32_t dim;             /* 1 (D1Q2) or 2 (D2Q4) */
+    int64_t nx, ny;          /* cells; ny == 1 when dim == 1; nx, ny >= 4 */
+    double dx;               /* uniform spacing (dy == dx) */
+    int32_t bc[4];           /* x-low, x-high, y-low, y-high: VLBM_BC_*; periodic must be set on both
+                                sides of an axis */
+    int32_t eos;             /* VLBM_EOS_IDEAL: P = (gamma-1) rho e (Eq. 15); VLBM_EOS_VDW (Eqs. 16-17) */
+    double gamma;            /* heat-capacity ratio; for vdW gamma = 1 + R/c_v */
+    double vdw_a, vdw_b, vdw_R;
+    double cfl;              /* target Courant number of the retargeting, c = s_max/CFL (Eq. 37) */
+    int32_t retarget_every;  /* 1: every step; K > 1: every K steps (forced if s_max > c);
+                                0: link speed frozen at c_fixed (no retarget, no landing) */
+    double c_fixed;          /* link speed when retarget_every == 0 */
+    int32_t sensor;          /* VLBM_SENSOR_*: OFF uses beta_const; A = Eq. 34; B = Eq. 35 */
+    double beta_const, beta_min, beta_max, c_sensor, eps_theta;
+    int32_t precision;       /* VLBM_FP64 or VLBM_FP32 (populations and per-cell arithmetic;
+                                clock, dt reduction and totals stay FP64) */
+    void* stream;            /* hipStream_t, or NULL for the default stream */
+} vlbm_config;
+
+/* Validate the configuration, allocate two population buffers, the clock and
+ * reduction ring and scratch on the current device.  Ownership of *out passes
+ * to the caller (release with vlbm_destroy).  EINVAL on a bad config, ENOMEM
+ * on allocation failure. */
+vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out);
+
+/* Release every device allocation of the context (synchronises its stream). */
+void vlbm_destroy(vlbm_ctx* ctx);
+
+/* Initial state (Sec. III.E: the link speed is chosen from the initial data):
+ * W0 (FP64, (dim+2, ny, nx)) is copied, c0 = s_max(W0)/CFL (or c_fixed),
+ * populations f = f^eq(W0; c0) (Eq. 20), t = 0, n = 0.  ENONHYPERBOLIC /
+ * ENONFINITE when W0 is not admissible. */
+vlbm_status vlbm_init(vlbm_ctx* ctx, const double* W0, int32_t W0_on_device);
+
+/* Advance exactly `nsteps` steps (fewer if t reaches t_end_cap, which then
+ * lands exactly; pass INFINITY for no cap).  *steps_taken (nullable) receives
+ * the steps executed.  On an EOS failure the state is left at the first
+ * inadmissible step and ENONHYPERBOLIC / ENONFINITE is returned. */
+vlbm_status vlbm_step(vlbm_ctx* ctx, int64_t nsteps, double t_end_cap, int64_t* steps_taken);
+
+/* Advance until t == t_end exactly (Sec. III.E, final-step landing).  No-op if
+ * t >= t_end already. */
+vlbm_status vlbm_run_to_time(vlbm_ctx* ctx, double t_end, int64_t* steps_taken);
+
+/* out[dim+2] (host) = sum_x W(x) dx^dim in FP64, by a fixed-order tree
+ * (deterministic).  Discrete conservation: Sec. III.A. */
+vlbm_status vlbm_conserved_totals(vlbm_ctx* ctx, double* out);
+
+/* W = sum_i f_i as FP64 (dim+2, ny, nx) into host or device memory. */
+vlbm_status vlbm_get_W(vlbm_ctx* ctx, double* out, int32_t out_on_device);
+
+/* beta(x) (Eqs. 34-35) of the current state: the field the next step uses,
+ * FP64 (ny, nx) into host or device memory. */
+vlbm_status vlbm_get_beta(vlbm_ctx* ctx, double* out, int32_t out_on_device);
+
+/* Raw populations in the context's precision, (2*dim, dim+2, ny, nx) without
+ * plane padding, into host or device memory. */
+vlbm_status vlbm_get_f(vlbm_ctx* ctx, void* out, int32_t out_on_device);
+
+/* Current time, link speed c and step count (synchronises). */
+vlbm_status vlbm_get_clock(vlbm_ctx* ctx, double* t, double* c, int64_t* n);
+
+/* Checkpoint / resume: the state is the populations plus (t, c, n) and the
+ * reductions of the current state.  `buf` is a device buffer of at least
+ * vlbm_state_bytes() bytes.  restore(save(x)) resumes bitwise. */
+size_t vlbm_state_bytes(const vlbm_ctx* ctx);
+vlbm_status vlbm_save(vlbm_ctx* ctx, void* buf);
+vlbm_status vlbm_restore(vlbm_ctx* ctx, const void* buf);
+
+/* Elements per population plane (padding included) and bytes of one
+ * population array (2*dim*(dim+2) planes) in the context's precision; the
+ * raw entry points below use this layout. */
+int64_t vlbm_plane_elems(const vlbm_ctx* ctx);
+size_t vlbm_population_bytes(const vlbm_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Raw, stream-ordered entry points for differentiation with the link speed
+ * frozen at c_fixed (retarget_every must be 0).  All pointers are device
+ * pointers.  A population array uses the padded plane layout above; `norms`
+ * arrays hold dim+3 doubles (s_max, then max_{x,alpha}|Q_alpha,k| for each
+ * component k, Eq. 30) describing the state they belong to.
+ * ------------------------------------------------------------------------- */
+
+/* f0 = f^eq(W0; c_fixed) (Eq. 20) and its norms.  W0: FP64 (dim+2, ny, nx). */
+vlbm_status vlbm_raw_init(vlbm_ctx* ctx, const double* W0, void* f0, double* norms0);
+
+/* One frozen-speed step f_out = step(f_in) (Eqs. 20-22, 28-35), reading the
+ * sensor normalisers from norms_in and writing the norms of f_out. */
+vlbm_status vlbm_raw_step(vlbm_ctx* ctx, const void* f_in, const double* norms_in, void* f_out,
+                          double* norms_out);
+
+/* Adjoint (vector-Jacobian product) of vlbm_raw_step at the state f_n with its
+ * norms: lam_n = (d step / d f_n)^T lam_np1, including the EOS closure, the
+ * sensor stencil and the max-normaliser (sub-gradient to the first arg-max in
+ * (alpha, y, x) order); clip derivative 1 on (0,1) and 0 outside; the
+ * derivative of the square root at 0 is taken as 0. */
+vlbm_status vlbm_raw_adjoint_step(vlbm_ctx* ctx, const void* f_n, const double* norms_n,
+                                  const void* lam_np1, void* lam_n);
+
+/* Adjoint of vlbm_raw_init: W0bar (FP64 (dim+2, ny, nx), overwritten) =
+ * (d f0/d W0)^T lam0 at the state W0. */
+vlbm_status vlbm_raw_init_adjoint(vlbm_ctx* ctx, const double* W0, const void* lam0, double* W0bar);
+
+/* W = sum_i f_i of a population array, FP64 (dim+2, ny, nx). */
+vlbm_status vlbm_raw_moments(vlbm_ctx* ctx, const void* f, double* W);
+
+/* Adjoint of vlbm_raw_moments: lam_i = Wbar for every direction i. */
+vlbm_status vlbm_raw_moments_adjoint(vlbm_ctx* ctx, const double* Wbar, void* lam);
+
+/* Message of the last failing call on this context (valid until the next call). */
+const char* vlbm_last_error(const vlbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VLBM_H */

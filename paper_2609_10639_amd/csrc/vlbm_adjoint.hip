@@ -1,0 +1,9 @@
+// placeholder, replaced by the adjoint kernels
+#include "vlbm_aux.hpp"
+namespace vlbm {
+size_t adjoint_partials_count(const KParams&) { return 1; }
+hipError_t launch_adjoint_step(const KParams&, bool, const void*, const double*, const void*, void*,
+                               const AdjScratch&, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_init_adjoint(const KParams&, bool, const double*, long long, const void*, double*, hipStream_t)
+{ return hipErrorNotSupported; }
+}

@@ -1,0 +1,560 @@
+// Host runtime of the VLBM library: configuration checks, device buffers,
+// the clock/reduction ring and the batched step loop behind the C ABI of
+// include/vlbm.h.
+//
+// Device state
+//   f[2]       two population buffers; state n lives in f[n & 1]
+//   ring       3 slots x 8 doubles: [t, c, s_max, M_0..M_{D+1}, -]; state n
+//              has its clock and reductions in slot n % 3
+//   stop_at    launches with index >= stop_at return immediately (landing or
+//              an inadmissible state), so a batch never overruns
+//   err        admissibility bits of the state stop_at
+// The host launches steps in batches without synchronising, then reads the
+// control block back once per batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/vlbm.h"
+#include "vlbm_aux.hpp"
+
+using namespace vlbm;
+
+struct vlbm_ctx {
+    vlbm_config cfg;
+    KParams kp;
+    int D, Q, NK, nplanes;
+    bool fp32;
+    size_t esize;
+    long long ncell, plane;
+    void* f[2] = {nullptr, nullptr};
+    double* ring = nullptr;
+    unsigned long long* stop_at = nullptr;
+    int* err = nullptr;
+    double* scratchW = nullptr;    // (NK, ncell) FP64
+    double* scratchB = nullptr;    // (ncell) FP64
+    double* partials = nullptr;    // totals partials
+    double* norms_scratch = nullptr;
+    double* host = nullptr;        // pinned readback: ring (24) + totals (4)
+    unsigned long long* host_u = nullptr;
+    int* raw_err = nullptr;
+    AdjScratch adj{};
+    hipStream_t stream;
+    long long n = 0;
+    double t = 0.0, c = 0.0;
+    bool initialised = false;
+    std::string msg;
+};
+
+namespace {
+
+vlbm_status fail(vlbm_ctx* ctx, vlbm_status st, const std::string& m)
+{
+    if (ctx) ctx->msg = m;
+    return st;
+}
+
+vlbm_status hip_fail(vlbm_ctx* ctx, hipError_t e, const char* where)
+{
+    return fail(ctx, VLBM_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr)                                      \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+vlbm_status err_status(int bits)
+{
+    if (bits & ERR_NONFINITE) return VLBM_ENONFINITE;
+    if (bits & ERR_NONHYP) return VLBM_ENONHYPERBOLIC;
+    return VLBM_OK;
+}
+
+// rows per segment of the D2Q4 march: enough wavefronts to fill every CU
+// once at the kernel's occupancy, without a partial second round
+int choose_seg_h(const KParams& p, bool fp32)
+{
+    if (const char* env = getenv("VLBM_SEG_H")) {
+        const int v = atoi(env);
+        if (v > 0) return std::min(v, p.ny);
+    }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    int per_cu = step_d2q4_blocks_per_cu(p, fp32);
+    if (per_cu <= 0) per_cu = 8;
+    const long long resident = (long long)cus * per_cu;
+    long long nsegs = std::max(1LL, resident / p.nstrips);
+    int h = (int)((p.ny + nsegs - 1) / nsegs);
+    h = std::max(h, 16);
+    return std::min(h, p.ny);
+}
+
+vlbm_status sync_readback(vlbm_ctx* ctx)
+{
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host, ctx->ring, 24 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host_u, ctx->stop_at, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync((char*)(ctx->host_u + 1), ctx->err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return VLBM_OK;
+}
+
+hipError_t launch_one(vlbm_ctx* ctx, long long n, double t_end)
+{
+    KStep s{};
+    double* slot = ctx->ring + 8 * (n % 3);
+    double* next = ctx->ring + 8 * ((n + 1) % 3);
+    double* after = ctx->ring + 8 * ((n + 2) % 3);
+    s.clock_in = slot;
+    s.clock_out = next;
+    s.red_in = slot + 2;
+    s.red_out = next + 2;
+    s.red_clear = after + 2;
+    s.stop_at = ctx->stop_at;
+    s.err = ctx->err;
+    s.n = n;
+    s.t_end = t_end;
+    const void* fin = ctx->f[n & 1];
+    void* fout = ctx->f[(n + 1) & 1];
+    return ctx->D == 2 ? launch_step_d2q4(ctx->kp, s, ctx->fp32, fin, fout, ctx->stream)
+                       : launch_step_d1q2(ctx->kp, s, ctx->fp32, fin, fout, ctx->stream);
+}
+
+// launch `count` steps from the host's step index, read back, update the mirror
+vlbm_status run_batch(vlbm_ctx* ctx, long long count, double t_end, long long* executed)
+{
+    const long long n0 = ctx->n;
+    for (long long k = 0; k < count; ++k) HIPCHK(ctx, launch_one(ctx, n0 + k, t_end));
+    vlbm_status st = sync_readback(ctx);
+    if (st != VLBM_OK) return st;
+    const unsigned long long stop = ctx->host_u[0];
+    int bits;
+    memcpy(&bits, (char*)(ctx->host_u + 1), sizeof(int));
+    long long nn = n0 + count;
+    if (stop != ~0ull && (long long)stop < nn) nn = (long long)stop;
+    ctx->n = nn;
+    const double* slot = ctx->host + 8 * (nn % 3);
+    ctx->t = slot[0];
+    ctx->c = slot[1];
+    *executed = nn - n0;
+    if (bits) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "inadmissible state (bits %d) at step %lld", bits, nn);
+        return fail(ctx, err_status(bits), buf);
+    }
+    return VLBM_OK;
+}
+
+bool check_config(const vlbm_config* c, std::string& why)
+{
+    if (c->dim != 1 && c->dim != 2) return why = "dim must be 1 or 2", false;
+    if (c->nx < 4 || c->nx > (1LL << 30)) return why = "nx out of range", false;
+    if (c->dim == 1 && c->ny != 1) return why = "ny must be 1 in 1-D", false;
+    if (c->dim == 2 && (c->ny < 4 || c->ny > (1LL << 30))) return why = "ny out of range", false;
+    if (c->nx * c->ny > (1LL << 31)) return why = "grid too large", false;
+    if (!(c->dx > 0) || !std::isfinite(c->dx)) return why = "dx must be positive", false;
+    for (int i = 0; i < 4; ++i)
+        if (c->bc[i] != VLBM_BC_PERIODIC && c->bc[i] != VLBM_BC_OUTFLOW) return why = "bad boundary kind", false;
+    if ((c->bc[0] == VLBM_BC_PERIODIC) != (c->bc[1] == VLBM_BC_PERIODIC))
+        return why = "periodic x needs both x sides periodic", false;
+    if (c->dim == 2 && (c->bc[2] == VLBM_BC_PERIODIC) != (c->bc[3] == VLBM_BC_PERIODIC))
+        return why = "periodic y needs both y sides periodic", false;
+    if (c->eos != VLBM_EOS_IDEAL && c->eos != VLBM_EOS_VDW) return why = "bad eos", false;
+    if (!(c->gamma > 1.0)) return why = "gamma must exceed 1", false;
+    if (c->eos == VLBM_EOS_VDW && (!(c->vdw_R > 0) || c->vdw_a < 0 || c->vdw_b < 0))
+        return why = "bad van der Waals constants", false;
+    if (c->retarget_every < 0) return why = "retarget_every must be >= 0", false;
+    if (c->retarget_every > 0 && !(c->cfl > 0 && c->cfl <= 1.0)) return why = "cfl must be in (0, 1]", false;
+    if (c->retarget_every == 0 && !(c->c_fixed > 0)) return why = "c_fixed must be positive", false;
+    if (c->sensor < 0 || c->sensor > 3) return why = "bad sensor", false;
+    auto okb = [](double b) { return b > 0.0 && b <= 1.0; };
+    if (c->sensor == VLBM_SENSOR_OFF && !okb(c->beta_const)) return why = "beta_const must be in (0, 1]", false;
+    if (c->sensor != VLBM_SENSOR_OFF &&
+        (!okb(c->beta_min) || !okb(c->beta_max) || c->beta_min > c->beta_max || !(c->c_sensor >= 0) ||
+         !(c->eps_theta > 0)))
+        return why = "bad sensor constants", false;
+    if (c->precision != VLBM_FP64 && c->precision != VLBM_FP32) return why = "bad precision", false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
+{
+    if (!cfg || !out) return VLBM_EINVAL;
+    *out = nullptr;
+    std::string why;
+    if (!check_config(cfg, why)) {
+        fprintf(stderr, "vlbm_create: %s\n", why.c_str());
+        return VLBM_EINVAL;
+    }
+    vlbm_ctx* ctx = new vlbm_ctx();
+    ctx->cfg = *cfg;
+    ctx->stream = (hipStream_t)cfg->stream;
+    ctx->D = cfg->dim;
+    ctx->Q = 2 * cfg->dim;
+    ctx->NK = cfg->dim + 2;
+    ctx->nplanes = ctx->Q * ctx->NK;
+    ctx->fp32 = cfg->precision == VLBM_FP32;
+    ctx->esize = ctx->fp32 ? 4 : 8;
+    ctx->ncell = cfg->nx * cfg->ny;
+    ctx->plane = (ctx->ncell + 63) / 64 * 64;
+
+    KParams& p = ctx->kp;
+    p.dim = cfg->dim;
+    p.nx = (int)cfg->nx;
+    p.ny = (int)cfg->ny;
+    p.plane = ctx->plane;
+    p.dx = cfg->dx;
+    for (int i = 0; i < 4; ++i) p.bc[i] = cfg->bc[i];
+    p.eos = cfg->eos;
+    p.gamma = cfg->gamma;
+    p.vdw_a = cfg->vdw_a;
+    p.vdw_b = cfg->vdw_b;
+    p.vdw_R = cfg->eos == VLBM_EOS_VDW ? cfg->vdw_R : 1.0;
+    p.inv_cv = (cfg->gamma - 1.0) / p.vdw_R;
+    p.cfl = cfg->cfl;
+    p.c_fixed = cfg->c_fixed;
+    p.retarget_every = cfg->retarget_every;
+    int sensor = cfg->sensor;
+    if (sensor == VLBM_SENSOR_AUTO) sensor = cfg->dim == 1 ? VLBM_SENSOR_A : VLBM_SENSOR_B;
+    if (cfg->dim == 1 && sensor == VLBM_SENSOR_B) sensor = VLBM_SENSOR_A;   // no vorticity in 1-D
+    p.sensor = sensor;
+    p.beta_const = cfg->beta_const;
+    p.beta_min = cfg->beta_min;
+    p.beta_max = cfg->beta_max;
+    p.c_sensor = cfg->c_sensor;
+    p.eps_theta = cfg->eps_theta;
+    p.nstrips = (p.nx + 57) / 58;
+    p.seg_h = p.ny;
+    p.nsegs = 1;
+    if (cfg->dim == 2) {
+        p.seg_h = choose_seg_h(p, ctx->fp32);
+        p.nsegs = (p.ny + p.seg_h - 1) / p.seg_h;
+    }
+
+    const size_t fbytes = (size_t)ctx->nplanes * ctx->plane * ctx->esize;
+    bool ok = hipMalloc(&ctx->f[0], fbytes) == hipSuccess && hipMalloc(&ctx->f[1], fbytes) == hipSuccess &&
+              hipMalloc(&ctx->ring, 24 * sizeof(double)) == hipSuccess &&
+              hipMalloc(&ctx->stop_at, sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc(&ctx->err, sizeof(int)) == hipSuccess &&
+              hipMalloc(&ctx->raw_err, sizeof(int)) == hipSuccess &&
+              hipMalloc(&ctx->scratchW, (size_t)ctx->NK * ctx->ncell * sizeof(double)) == hipSuccess &&
+              hipMalloc(&ctx->scratchB, (size_t)ctx->ncell * sizeof(double)) == hipSuccess &&
+              hipMalloc(&ctx->partials, (size_t)totals_nparts(ctx->ncell) * 4 * sizeof(double) + 64) == hipSuccess &&
+              hipMalloc(&ctx->norms_scratch, 16 * sizeof(double)) == hipSuccess &&
+              hipHostMalloc((void**)&ctx->host, 48 * sizeof(double)) == hipSuccess &&
+              hipHostMalloc((void**)&ctx->host_u, 4 * sizeof(unsigned long long)) == hipSuccess;
+    if (ok) {
+        ctx->adj.nparts = (int)adjoint_partials_count(p);
+        ok = hipMalloc(&ctx->adj.seeds, (size_t)2 * ctx->ncell * sizeof(double)) == hipSuccess &&
+             hipMalloc(&ctx->adj.partials, (size_t)ctx->adj.nparts * 4 * sizeof(double) + 64) == hipSuccess &&
+             hipMalloc(&ctx->adj.argmax, 8 * sizeof(unsigned long long)) == hipSuccess;
+        ctx->adj.err = ctx->raw_err;
+    }
+    if (!ok) {
+        vlbm_destroy(ctx);
+        return VLBM_ENOMEM;
+    }
+    if (launch_reset_ctl(ctx->ring, ctx->stop_at, ctx->err, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        vlbm_destroy(ctx);
+        return VLBM_EDEVICE;
+    }
+    *out = ctx;
+    return VLBM_OK;
+}
+
+void vlbm_destroy(vlbm_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void* p : {ctx->f[0], ctx->f[1], (void*)ctx->ring, (void*)ctx->stop_at, (void*)ctx->err,
+                    (void*)ctx->raw_err, (void*)ctx->scratchW, (void*)ctx->scratchB, (void*)ctx->partials,
+                    (void*)ctx->norms_scratch, (void*)ctx->adj.seeds, (void*)ctx->adj.partials,
+                    (void*)ctx->adj.argmax})
+        if (p) (void)hipFree(p);
+    if (ctx->host) (void)hipHostFree(ctx->host);
+    if (ctx->host_u) (void)hipHostFree(ctx->host_u);
+    delete ctx;
+}
+
+vlbm_status vlbm_init(vlbm_ctx* ctx, const double* W0, int32_t W0_on_device)
+{
+    if (!ctx || !W0) return fail(ctx, VLBM_EINVAL, "null argument");
+    const size_t wbytes = (size_t)ctx->NK * ctx->ncell * sizeof(double);
+    HIPCHK(ctx, hipMemcpyAsync(ctx->scratchW, W0, wbytes,
+                               W0_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, launch_reset_ctl(ctx->ring, ctx->stop_at, ctx->err, ctx->stream));
+    HIPCHK(ctx, launch_init(ctx->kp, ctx->fp32, ctx->scratchW, ctx->ncell, ctx->ring, ctx->err,
+                            ctx->cfg.retarget_every == 0, ctx->f[0], ctx->stream));
+    vlbm_status st = sync_readback(ctx);
+    if (st != VLBM_OK) return st;
+    int bits;
+    memcpy(&bits, (char*)(ctx->host_u + 1), sizeof(int));
+    ctx->n = 0;
+    ctx->t = ctx->host[0];
+    ctx->c = ctx->host[1];
+    ctx->initialised = false;
+    if (bits) return fail(ctx, err_status(bits), "initial state not admissible");
+    if (!(ctx->c > 0) || !std::isfinite(ctx->c)) return fail(ctx, VLBM_EINVAL, "initial link speed not positive");
+    ctx->initialised = true;
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_step(vlbm_ctx* ctx, int64_t nsteps, double t_end_cap, int64_t* steps_taken)
+{
+    if (steps_taken) *steps_taken = 0;
+    if (!ctx || nsteps < 0) return fail(ctx, VLBM_EINVAL, "bad argument");
+    if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
+    if (std::isnan(t_end_cap)) return fail(ctx, VLBM_EINVAL, "t_end_cap is NaN");
+    if (nsteps == 0 || ctx->t >= t_end_cap) return VLBM_OK;
+    HIPCHK(ctx, launch_reset_stop(ctx->stop_at, ctx->err, ctx->stream));
+    long long done = 0;
+    vlbm_status st = run_batch(ctx, nsteps, std::isinf(t_end_cap) ? HUGE_VAL : t_end_cap, &done);
+    if (steps_taken) *steps_taken = done;
+    return st;
+}
+
+vlbm_status vlbm_run_to_time(vlbm_ctx* ctx, double t_end, int64_t* steps_taken)
+{
+    if (steps_taken) *steps_taken = 0;
+    if (!ctx || !std::isfinite(t_end)) return fail(ctx, VLBM_EINVAL, "bad argument");
+    if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
+    if (ctx->cfg.retarget_every == 0)
+        ; // frozen speed: the landing step still shortens dt
+    long long total = 0;
+    HIPCHK(ctx, launch_reset_stop(ctx->stop_at, ctx->err, ctx->stream));
+    while (ctx->t < t_end) {
+        // steps left at the current time step, plus a margin; extra launches
+        // after the landing step return at once
+        const double dt = ctx->cfg.dx / ctx->c;
+        double est = std::ceil((t_end - ctx->t) / dt);
+        long long batch = (long long)std::min(std::max(est * 1.05 + 4.0, 1.0), 8192.0);
+        long long done = 0;
+        vlbm_status st = run_batch(ctx, batch, t_end, &done);
+        total += done;
+        if (st != VLBM_OK) {
+            if (steps_taken) *steps_taken = total;
+            return st;
+        }
+        if (done < batch) break;   // landed
+    }
+    if (steps_taken) *steps_taken = total;
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_conserved_totals(vlbm_ctx* ctx, double* out)
+{
+    if (!ctx || !out) return fail(ctx, VLBM_EINVAL, "null argument");
+    if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
+    double* dout = ctx->norms_scratch;
+    HIPCHK(ctx, launch_totals(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, ctx->f[ctx->n & 1], ctx->partials, dout,
+                              ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host + 24, dout, ctx->NK * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const double vol = ctx->D == 1 ? ctx->cfg.dx : ctx->cfg.dx * ctx->cfg.dx;
+    for (int k = 0; k < ctx->NK; ++k) out[k] = ctx->host[24 + k] * vol;
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_get_W(vlbm_ctx* ctx, double* out, int32_t out_on_device)
+{
+    if (!ctx || !out) return fail(ctx, VLBM_EINVAL, "null argument");
+    if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
+    double* dst = out_on_device ? out : ctx->scratchW;
+    HIPCHK(ctx, launch_moments(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, ctx->f[ctx->n & 1], dst, ctx->stream));
+    if (!out_on_device)
+        HIPCHK(ctx, hipMemcpyAsync(out, dst, (size_t)ctx->NK * ctx->ncell * sizeof(double), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_get_beta(vlbm_ctx* ctx, double* out, int32_t out_on_device)
+{
+    if (!ctx || !out) return fail(ctx, VLBM_EINVAL, "null argument");
+    if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
+    KParams p = ctx->kp;
+    p.c_fixed = ctx->c;
+    KStep s{};
+    double* slot = ctx->ring + 8 * (ctx->n % 3);
+    s.clock_in = slot;
+    s.red_in = slot + 2;
+    s.red_out = ctx->norms_scratch;
+    s.err = ctx->raw_err;
+    s.frozen = 1;
+    s.probe = 1;
+    s.beta_out = out_on_device ? out : ctx->scratchB;
+    s.t_end = HUGE_VAL;
+    const void* fin = ctx->f[ctx->n & 1];
+    HIPCHK(ctx, ctx->D == 2 ? launch_step_d2q4(p, s, ctx->fp32, fin, nullptr, ctx->stream)
+                            : launch_step_d1q2(p, s, ctx->fp32, fin, nullptr, ctx->stream));
+    if (!out_on_device)
+        HIPCHK(ctx, hipMemcpyAsync(out, ctx->scratchB, (size_t)ctx->ncell * sizeof(double), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_get_f(vlbm_ctx* ctx, void* out, int32_t out_on_device)
+{
+    if (!ctx || !out) return fail(ctx, VLBM_EINVAL, "null argument");
+    if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
+    const size_t bytes = (size_t)ctx->nplanes * ctx->ncell * ctx->esize;
+    if (out_on_device) {
+        HIPCHK(ctx, launch_unpad(ctx->nplanes, ctx->plane, ctx->ncell, ctx->fp32, ctx->f[ctx->n & 1], out,
+                                 ctx->stream));
+    } else {
+        void* tmp = ctx->f[(ctx->n + 1) & 1];   // the spare buffer is free between steps
+        HIPCHK(ctx, launch_unpad(ctx->nplanes, ctx->plane, ctx->ncell, ctx->fp32, ctx->f[ctx->n & 1], tmp,
+                                 ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_get_clock(vlbm_ctx* ctx, double* t, double* c, int64_t* n)
+{
+    if (!ctx) return VLBM_EINVAL;
+    if (t) *t = ctx->t;
+    if (c) *c = ctx->c;
+    if (n) *n = ctx->n;
+    return VLBM_OK;
+}
+
+size_t vlbm_state_bytes(const vlbm_ctx* ctx)
+{
+    if (!ctx) return 0;
+    return (size_t)ctx->nplanes * ctx->plane * ctx->esize + 32 * sizeof(double);
+}
+
+vlbm_status vlbm_save(vlbm_ctx* ctx, void* buf)
+{
+    if (!ctx || !buf) return fail(ctx, VLBM_EINVAL, "null argument");
+    if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
+    const size_t fb = (size_t)ctx->nplanes * ctx->plane * ctx->esize;
+    HIPCHK(ctx, hipMemcpyAsync(buf, ctx->f[ctx->n & 1], fb, hipMemcpyDeviceToDevice, ctx->stream));
+    // the current slot (clock + reductions of the state) and the step count
+    HIPCHK(ctx, hipMemcpyAsync((char*)buf + fb, ctx->ring + 8 * (ctx->n % 3), 8 * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->host[24] = (double)ctx->n;
+    HIPCHK(ctx, hipMemcpyAsync((char*)buf + fb + 8 * sizeof(double), ctx->host + 24, sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_restore(vlbm_ctx* ctx, const void* buf)
+{
+    if (!ctx || !buf) return fail(ctx, VLBM_EINVAL, "null argument");
+    const size_t fb = (size_t)ctx->nplanes * ctx->plane * ctx->esize;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host + 24, (const char*)buf + fb, 9 * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const long long n = (long long)ctx->host[32];
+    if (n < 0) return fail(ctx, VLBM_EINVAL, "corrupt checkpoint");
+    HIPCHK(ctx, launch_reset_ctl(ctx->ring, ctx->stop_at, ctx->err, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->f[n & 1], buf, fb, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->ring + 8 * (n % 3), (const char*)buf + fb, 8 * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->n = n;
+    ctx->t = ctx->host[24];
+    ctx->c = ctx->host[25];
+    ctx->initialised = true;
+    return VLBM_OK;
+}
+
+int64_t vlbm_plane_elems(const vlbm_ctx* ctx) { return ctx ? ctx->plane : 0; }
+
+size_t vlbm_population_bytes(const vlbm_ctx* ctx)
+{
+    return ctx ? (size_t)ctx->nplanes * ctx->plane * ctx->esize : 0;
+}
+
+// ------------------------------------------------------------------ raw entry points
+
+static vlbm_status need_frozen(vlbm_ctx* ctx)
+{
+    if (!ctx) return VLBM_EINVAL;
+    if (ctx->cfg.retarget_every != 0) return fail(ctx, VLBM_EINVAL, "raw entry points need retarget_every == 0");
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_raw_init(vlbm_ctx* ctx, const double* W0, void* f0, double* norms0)
+{
+    if (vlbm_status st = need_frozen(ctx)) return st;
+    if (!W0 || !f0 || !norms0) return fail(ctx, VLBM_EINVAL, "null argument");
+    HIPCHK(ctx, launch_zero(ctx->norms_scratch, 8, ctx->stream));
+    HIPCHK(ctx, launch_init(ctx->kp, ctx->fp32, W0, ctx->ncell, ctx->norms_scratch, ctx->raw_err, 1, f0,
+                            ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(norms0, ctx->norms_scratch + 2, (ctx->NK + 1) * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_raw_step(vlbm_ctx* ctx, const void* f_in, const double* norms_in, void* f_out, double* norms_out)
+{
+    if (vlbm_status st = need_frozen(ctx)) return st;
+    if (!f_in || !f_out || !norms_in || !norms_out) return fail(ctx, VLBM_EINVAL, "null argument");
+    HIPCHK(ctx, launch_zero(norms_out, ctx->NK + 1, ctx->stream));
+    KStep s{};
+    s.red_in = norms_in;
+    s.red_out = norms_out;
+    s.err = ctx->raw_err;
+    s.frozen = 1;
+    s.t_end = HUGE_VAL;
+    HIPCHK(ctx, ctx->D == 2 ? launch_step_d2q4(ctx->kp, s, ctx->fp32, f_in, f_out, ctx->stream)
+                            : launch_step_d1q2(ctx->kp, s, ctx->fp32, f_in, f_out, ctx->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_raw_adjoint_step(vlbm_ctx* ctx, const void* f_n, const double* norms_n, const void* lam_np1,
+                                  void* lam_n)
+{
+    if (vlbm_status st = need_frozen(ctx)) return st;
+    if (!f_n || !norms_n || !lam_np1 || !lam_n) return fail(ctx, VLBM_EINVAL, "null argument");
+    if (lam_np1 == lam_n) return fail(ctx, VLBM_EINVAL, "lam_np1 and lam_n must differ");
+    HIPCHK(ctx, launch_adjoint_step(ctx->kp, ctx->fp32, f_n, norms_n, lam_np1, lam_n, ctx->adj, ctx->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_raw_init_adjoint(vlbm_ctx* ctx, const double* W0, const void* lam0, double* W0bar)
+{
+    if (vlbm_status st = need_frozen(ctx)) return st;
+    if (!W0 || !lam0 || !W0bar) return fail(ctx, VLBM_EINVAL, "null argument");
+    HIPCHK(ctx, launch_init_adjoint(ctx->kp, ctx->fp32, W0, ctx->ncell, lam0, W0bar, ctx->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_raw_moments(vlbm_ctx* ctx, const void* f, double* W)
+{
+    if (!ctx || !f || !W) return fail(ctx, VLBM_EINVAL, "null argument");
+    HIPCHK(ctx, launch_moments(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, f, W, ctx->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_raw_moments_adjoint(vlbm_ctx* ctx, const double* Wbar, void* lam)
+{
+    if (!ctx || !Wbar || !lam) return fail(ctx, VLBM_EINVAL, "null argument");
+    HIPCHK(ctx, launch_moments_adj(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, Wbar, lam, ctx->stream));
+    return VLBM_OK;
+}
+
+const char* vlbm_last_error(const vlbm_ctx* ctx) { return ctx ? ctx->msg.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,307 @@
+// Auxiliary kernels of the VLBM library: control-block reset, initial state
+// (reductions of W0 and the equilibrium populations), conserved totals,
+// moments and layout copies.
+#include "vlbm_aux.hpp"
+
+namespace vlbm {
+
+__global__ void k_reset_ctl(double* ring, unsigned long long* stop_at, int* err)
+{
+    const int i = threadIdx.x;
+    if (i < 24) ring[i] = 0.0;
+    if (i == 0) {
+        *stop_at = ~0ull;
+        *err = 0;
+    }
+}
+
+__global__ void k_reset_stop(unsigned long long* stop_at, int* err)
+{
+    if (threadIdx.x == 0) {
+        *stop_at = ~0ull;
+        *err = 0;
+    }
+}
+
+__global__ void k_zero(double* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// primitive closure of one FP64 cell of W (component stride `cs`)
+template <int EOS>
+__device__ __forceinline__ void prim_cell(const Gas<double>& g, int D, const double* W, long long cs, double& rho,
+                                          double* u, double& e, double& P, double& E)
+{
+    rho = W[0];
+    const double irho = 1.0 / rho;
+    double ke = 0.0;
+    for (int a = 0; a < D; ++a) {
+        u[a] = W[(1 + a) * cs] * irho;
+        ke += u[a] * u[a];
+    }
+    E = W[(D + 1) * cs];
+    e = E * irho - 0.5 * ke;
+    P = eos_pressure<double, EOS>(g, rho, e);
+}
+
+// Reductions of the initial state: s_max (Eq. 36) and M_k (Eq. 30) into
+// red_out[0], red_out[1 + k]; admissibility bits into err.
+template <int EOS>
+__global__ void k_init_reduce(KParams p, const double* __restrict__ W, long long ncell, double* red_out, int* err)
+{
+    const Gas<double> g = make_gas<double>(p);
+    const int D = p.dim;
+    double smax = 0.0, M[4] = {0, 0, 0, 0};
+    int bits = 0;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
+         c += (long long)gridDim.x * blockDim.x) {
+        double rho, u[2] = {0, 0}, e, P, E;
+        prim_cell<EOS>(g, D, W + c, ncell, rho, u, e, P, E);
+        const double cs2 = eos_cs2<double, EOS>(g, rho, e);
+        bits |= eos_check<double, EOS>(g, rho, e, cs2);
+        const double cs = sqrt(cs2 > 0.0 ? cs2 : 0.0);
+        for (int a = 0; a < D; ++a) {
+            smax = fmax(smax, fabs(u[a]) + cs);
+            const double m = W[(1 + a) * ncell + c];
+            M[0] = fmax(M[0], fabs(m));
+            for (int b = 0; b < D; ++b) M[1 + b] = fmax(M[1 + b], fabs(m * u[b] + (a == b ? P : 0.0)));
+            M[D + 1] = fmax(M[D + 1], fabs((E + P) * u[a]));
+        }
+    }
+    KStep s{};
+    s.red_out = red_out;
+    s.err = err;
+    wave_publish(s, smax, M, D + 2, bits);
+}
+
+// f = f^eq(W0; c0) (Eq. 20); c0 = s_max/CFL from red (or c_fixed).  Block 0
+// writes the clock (t = 0, c0) of slot 0.
+template <typename T, int EOS>
+__global__ void k_init_eq(KParams p, const double* __restrict__ W, long long ncell, double* slot0, int frozen,
+                          T* __restrict__ f)
+{
+    const double c0 = frozen ? p.c_fixed : slot0[2] / p.cfl;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        slot0[0] = 0.0;
+        slot0[1] = c0;
+    }
+    const Gas<double> g = make_gas<double>(p);
+    const int D = p.dim, NK = D + 2;
+    const double inv2c = 0.5 / c0, w = 1.0 / (2.0 * D);
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
+         c += (long long)gridDim.x * blockDim.x) {
+        double rho, u[2] = {0, 0}, e, P, E;
+        prim_cell<EOS>(g, D, W + c, ncell, rho, u, e, P, E);
+        for (int a = 0; a < D; ++a) {
+            const double m = W[(1 + a) * ncell + c];
+            double q[4];
+            q[0] = m;
+            for (int b = 0; b < D; ++b) q[1 + b] = m * u[b] + (a == b ? P : 0.0);
+            q[D + 1] = (E + P) * u[a];
+            for (int k = 0; k < NK; ++k) {
+                const double wk = w * W[k * ncell + c];
+                f[((2 * a) * NK + k) * p.plane + c] = (T)(wk + q[k] * inv2c);
+                f[((2 * a + 1) * NK + k) * p.plane + c] = (T)(wk - q[k] * inv2c);
+            }
+        }
+    }
+}
+
+// W = sum_i f_i in FP64, (NK, ncell)
+template <typename T>
+__global__ void k_moments(int D, long long plane, long long ncell, const T* __restrict__ f, double* __restrict__ W)
+{
+    const int NK = D + 2, Q = 2 * D;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
+         c += (long long)gridDim.x * blockDim.x)
+        for (int k = 0; k < NK; ++k) {
+            double acc = 0.0;
+            for (int i = 0; i < Q; ++i) acc += (double)f[(i * NK + k) * plane + c];
+            W[k * ncell + c] = acc;
+        }
+}
+
+// lam_i = Wbar for every direction i (adjoint of k_moments)
+template <typename T>
+__global__ void k_moments_adj(int D, long long plane, long long ncell, const double* __restrict__ Wbar,
+                              T* __restrict__ lam)
+{
+    const int NK = D + 2, Q = 2 * D;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
+         c += (long long)gridDim.x * blockDim.x)
+        for (int k = 0; k < NK; ++k) {
+            const T v = (T)Wbar[k * ncell + c];
+            for (int i = 0; i < Q; ++i) lam[(i * NK + k) * plane + c] = v;
+        }
+}
+
+// Deterministic FP64 totals: each block sums a fixed set of cells with a fixed
+// tree; a second single-block pass sums the block partials in order.
+constexpr int kTotBlock = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(kTotBlock) k_totals_partial(int D, long long plane, long long ncell,
+                                                               const T* __restrict__ f, double* partials)
+{
+    __shared__ double sh[4][kTotBlock];
+    const int NK = D + 2, Q = 2 * D;
+    double acc[4] = {0, 0, 0, 0};
+    for (long long c = blockIdx.x * (long long)kTotBlock + threadIdx.x; c < ncell;
+         c += (long long)gridDim.x * kTotBlock)
+        for (int k = 0; k < NK; ++k) {
+            double w = 0.0;
+            for (int i = 0; i < Q; ++i) w += (double)f[(i * NK + k) * plane + c];
+            acc[k] += w;
+        }
+    for (int k = 0; k < NK; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = kTotBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < NK; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NK; ++k) partials[blockIdx.x * 4 + k] = sh[k][0];
+}
+
+__global__ void __launch_bounds__(kTotBlock) k_totals_final(int NK, int nparts, const double* partials, double* out)
+{
+    __shared__ double sh[4][kTotBlock];
+    double acc[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nparts; b += kTotBlock)
+        for (int k = 0; k < NK; ++k) acc[k] += partials[b * 4 + k];
+    for (int k = 0; k < NK; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = kTotBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < NK; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NK; ++k) out[k] = sh[k][0];
+}
+
+// populations without plane padding: out[j][cell] = f[j * plane + cell]
+template <typename T>
+__global__ void k_unpad(int nplanes, long long plane, long long ncell, const T* __restrict__ f, T* __restrict__ out)
+{
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
+         c += (long long)gridDim.x * blockDim.x)
+        for (int j = 0; j < nplanes; ++j) out[j * ncell + c] = f[j * plane + c];
+}
+
+// ------------------------------------------------------------------ launchers
+
+static unsigned grid_for(long long n, int block)
+{
+    long long g = (n + block - 1) / block;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+hipError_t launch_reset_ctl(double* ring, unsigned long long* stop_at, int* err, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, st, ring, stop_at, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_stop(unsigned long long* stop_at, int* err, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reset_stop, dim3(1), dim3(64), 0, st, stop_at, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero, dim3((n + 63) / 64), dim3(64), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const KParams& p, bool fp32, const double* W, long long ncell, double* slot0, int* err,
+                       int frozen, void* f, hipStream_t st)
+{
+    const unsigned grid = grid_for(ncell, 256);
+    if (p.eos == 0)
+        hipLaunchKernelGGL(k_init_reduce<0>, dim3(grid), dim3(256), 0, st, p, W, ncell, slot0 + 2, err);
+    else
+        hipLaunchKernelGGL(k_init_reduce<1>, dim3(grid), dim3(256), 0, st, p, W, ncell, slot0 + 2, err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define VLBM_INIT(T, E) hipLaunchKernelGGL((k_init_eq<T, E>), dim3(grid), dim3(256), 0, st, p, W, ncell, slot0, frozen, (T*)f)
+    if (fp32) {
+        if (p.eos == 0) VLBM_INIT(float, 0); else VLBM_INIT(float, 1);
+    } else {
+        if (p.eos == 0) VLBM_INIT(double, 0); else VLBM_INIT(double, 1);
+    }
+#undef VLBM_INIT
+    return hipGetLastError();
+}
+
+hipError_t launch_init_reduce_only(const KParams& p, const double* W, long long ncell, double* red_out, int* err,
+                                   hipStream_t st)
+{
+    const unsigned grid = grid_for(ncell, 256);
+    if (p.eos == 0)
+        hipLaunchKernelGGL(k_init_reduce<0>, dim3(grid), dim3(256), 0, st, p, W, ncell, red_out, err);
+    else
+        hipLaunchKernelGGL(k_init_reduce<1>, dim3(grid), dim3(256), 0, st, p, W, ncell, red_out, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int D, long long plane, long long ncell, bool fp32, const void* f, double* W, hipStream_t st)
+{
+    const unsigned grid = grid_for(ncell, 256);
+    if (fp32)
+        hipLaunchKernelGGL(k_moments<float>, dim3(grid), dim3(256), 0, st, D, plane, ncell, (const float*)f, W);
+    else
+        hipLaunchKernelGGL(k_moments<double>, dim3(grid), dim3(256), 0, st, D, plane, ncell, (const double*)f, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_adj(int D, long long plane, long long ncell, bool fp32, const double* Wbar, void* lam,
+                              hipStream_t st)
+{
+    const unsigned grid = grid_for(ncell, 256);
+    if (fp32)
+        hipLaunchKernelGGL(k_moments_adj<float>, dim3(grid), dim3(256), 0, st, D, plane, ncell, Wbar, (float*)lam);
+    else
+        hipLaunchKernelGGL(k_moments_adj<double>, dim3(grid), dim3(256), 0, st, D, plane, ncell, Wbar, (double*)lam);
+    return hipGetLastError();
+}
+
+int totals_nparts(long long ncell)
+{
+    return (int)grid_for(ncell, kTotBlock) > 1024 ? 1024 : (int)grid_for(ncell, kTotBlock);
+}
+
+hipError_t launch_totals(int D, long long plane, long long ncell, bool fp32, const void* f, double* partials,
+                         double* out, hipStream_t st)
+{
+    const int nparts = totals_nparts(ncell);
+    if (fp32)
+        hipLaunchKernelGGL(k_totals_partial<float>, dim3(nparts), dim3(kTotBlock), 0, st, D, plane, ncell,
+                           (const float*)f, partials);
+    else
+        hipLaunchKernelGGL(k_totals_partial<double>, dim3(nparts), dim3(kTotBlock), 0, st, D, plane, ncell,
+                           (const double*)f, partials);
+    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(kTotBlock), 0, st, D + 2, nparts, partials, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpad(int nplanes, long long plane, long long ncell, bool fp32, const void* f, void* out,
+                        hipStream_t st)
+{
+    const unsigned grid = grid_for(ncell, 256);
+    if (fp32)
+        hipLaunchKernelGGL(k_unpad<float>, dim3(grid), dim3(256), 0, st, nplanes, plane, ncell, (const float*)f,
+                           (float*)out);
+    else
+        hipLaunchKernelGGL(k_unpad<double>, dim3(grid), dim3(256), 0, st, nplanes, plane, ncell, (const double*)f,
+                           (double*)out);
+    return hipGetLastError();
+}
+
+}  // namespace vlbm

@@ -1,0 +1,45 @@
+// Internal launcher declarations of the VLBM library (not part of the ABI).
+#pragma once
+
+#include "vlbm_common.hpp"
+
+namespace vlbm {
+
+hipError_t launch_step_d2q4(const KParams& p, const KStep& s, bool fp32, const void* fin, void* fout,
+                            hipStream_t st);
+hipError_t launch_step_d1q2(const KParams& p, const KStep& s, bool fp32, const void* fin, void* fout,
+                            hipStream_t st);
+int step_d2q4_blocks_per_cu(const KParams& p, bool fp32);
+
+hipError_t launch_reset_ctl(double* ring, unsigned long long* stop_at, int* err, hipStream_t st);
+hipError_t launch_reset_stop(unsigned long long* stop_at, int* err, hipStream_t st);
+hipError_t launch_zero(double* p, int n, hipStream_t st);
+hipError_t launch_init(const KParams& p, bool fp32, const double* W, long long ncell, double* slot0, int* err,
+                       int frozen, void* f, hipStream_t st);
+hipError_t launch_init_reduce_only(const KParams& p, const double* W, long long ncell, double* red_out, int* err,
+                                   hipStream_t st);
+hipError_t launch_moments(int D, long long plane, long long ncell, bool fp32, const void* f, double* W,
+                          hipStream_t st);
+hipError_t launch_moments_adj(int D, long long plane, long long ncell, bool fp32, const double* Wbar, void* lam,
+                              hipStream_t st);
+int totals_nparts(long long ncell);
+hipError_t launch_totals(int D, long long plane, long long ncell, bool fp32, const void* f, double* partials,
+                         double* out, hipStream_t st);
+hipError_t launch_unpad(int nplanes, long long plane, long long ncell, bool fp32, const void* f, void* out,
+                        hipStream_t st);
+
+// adjoint (vlbm_adjoint.hip)
+struct AdjScratch {
+    double* seeds;        // per-cell sensor seeds, 2 planes of ncell (FP64)
+    double* partials;     // per-block partial sums for the normaliser adjoint
+    int nparts;
+    unsigned long long* argmax;  // first arg-max index per component
+    int* err;
+};
+size_t adjoint_partials_count(const KParams& p);
+hipError_t launch_adjoint_step(const KParams& p, bool fp32, const void* f_n, const double* norms_n,
+                               const void* lam_np1, void* lam_n, const AdjScratch& sc, hipStream_t st);
+hipError_t launch_init_adjoint(const KParams& p, bool fp32, const double* W0, long long ncell, const void* lam0,
+                               double* W0bar, hipStream_t st);
+
+}  // namespace vlbm

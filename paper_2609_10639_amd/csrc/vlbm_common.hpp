@@ -1,0 +1,202 @@
+// Internal definitions shared by the HIP kernels and the host runtime of the
+// VLBM library (arXiv 2609.10639).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vlbm {
+
+// Static problem parameters, passed by value to every kernel.
+struct KParams {
+    int dim, nx, ny;
+    long long plane;          // elements per population plane (padded)
+    double dx;
+    int bc[4];                // x-lo, x-hi, y-lo, y-hi: 0 periodic, 1 outflow (clamped ghost)
+    int eos;                  // 0 ideal, 1 van der Waals
+    double gamma, vdw_a, vdw_b, vdw_R, inv_cv;
+    double cfl, c_fixed;
+    int retarget_every;
+    int sensor;               // resolved: 0 off, 1 A (no gate), 2 B (Ducros gate)
+    double beta_const, beta_min, beta_max, c_sensor, eps_theta;
+    int nstrips, seg_h, nsegs; // D2Q4 tiling: strips of columns x segments of rows
+};
+
+// Per-launch control: where the clock and the reductions of the current state
+// are read from and where those of the next state go.
+//
+// A ring slot is 8 doubles: [0] t, [1] c, [2] s_max, [3 + k] max|Q_alpha,k|.
+// Step n reads slot n%3, writes the clock and accumulates the reductions of the
+// new state into slot (n+1)%3, and clears the reductions of slot (n+2)%3.
+struct KStep {
+    const double* clock_in;        // t, c of the current state
+    double* clock_out;             // t, c after the step (block 0 writes)
+    const double* red_in;          // s_max, M_k of the current state
+    double* red_out;               // s_max, M_k of the new state (atomic max)
+    double* red_clear;             // reductions to zero (nullable)
+    unsigned long long* stop_at;   // steps with n >= *stop_at return at once (nullable)
+    int* err;                      // error bits (1: non-hyperbolic, 2: non-finite)
+    long long n;                   // index of this step
+    double t_end;                  // landing time (HUGE_VAL: none)
+    int frozen;                    // 1: c = c_fixed, no clock update, no landing
+    int probe;                     // 1: write beta of the current state to beta_out, no populations
+    double* beta_out;              // probe output, FP64 (ny, nx)
+};
+
+constexpr int ERR_NONHYP = 1;
+constexpr int ERR_NONFINITE = 2;
+
+// ------------------------------------------------------------- device helpers
+
+template <typename T>
+struct Gas {
+    T gm1, gamma, a, b, R, inv_cv;
+};
+
+template <typename T>
+__device__ __forceinline__ Gas<T> make_gas(const KParams& p)
+{
+    Gas<T> g;
+    g.gamma = (T)p.gamma;
+    g.gm1 = (T)(p.gamma - 1.0);
+    g.a = (T)p.vdw_a;
+    g.b = (T)p.vdw_b;
+    g.R = (T)p.vdw_R;
+    g.inv_cv = (T)p.inv_cv;
+    return g;
+}
+
+// Pressure P(rho, e): ideal gas Eq. 15; van der Waals Eqs. 16-17 with
+// T = (e + a rho)/c_v.
+template <typename T, int EOS>
+__device__ __forceinline__ T eos_pressure(const Gas<T>& g, T rho, T e)
+{
+    if constexpr (EOS == 0) {
+        return g.gm1 * rho * e;
+    } else {
+        const T temp = (e + g.a * rho) * g.inv_cv;
+        return g.R * rho * temp / ((T)1 - g.b * rho) - g.a * rho * rho;
+    }
+}
+
+// Frozen isentropic sound speed squared (Eq. 13) in closed form:
+// ideal gamma (gamma-1) e; van der Waals gamma R T/(1 - b rho)^2 - 2 a rho.
+template <typename T, int EOS>
+__device__ __forceinline__ T eos_cs2(const Gas<T>& g, T rho, T e)
+{
+    if constexpr (EOS == 0) {
+        return g.gamma * g.gm1 * e;
+    } else {
+        const T temp = (e + g.a * rho) * g.inv_cv;
+        const T d = (T)1 - g.b * rho;
+        return g.gamma * g.R * temp / (d * d) - (T)2 * g.a * rho;
+    }
+}
+
+// Admissibility bits of a state (Eq. 14 and the domain of the vdW closure).
+template <typename T, int EOS>
+__device__ __forceinline__ int eos_check(const Gas<T>& g, T rho, T e, T cs2)
+{
+    int bits = 0;
+    if (!(rho > (T)0) || !(cs2 > (T)0)) bits |= ERR_NONHYP;
+    if constexpr (EOS == 1) {
+        if (!((T)1 - g.b * rho > (T)0)) bits |= ERR_NONHYP;
+    }
+    if (!isfinite(rho) || !isfinite(e) || !isfinite(cs2)) bits |= ERR_NONFINITE;
+    return bits;
+}
+
+// Clock logic of one step (Sec. III.E): retarget c = s_max/CFL (Eq. 37), dt =
+// dx/c, final-step landing.  Returns false when the step must not run.
+__device__ __forceinline__ bool step_clock(const KParams& p, const KStep& s, double& c_old,
+                                           double& c_new, double& t, double& dt, bool& last)
+{
+    last = false;
+    t = 0.0;
+    dt = 0.0;
+    if (s.frozen) {
+        c_old = c_new = p.c_fixed;
+        return true;
+    }
+    if (s.stop_at && (unsigned long long)s.n >= *s.stop_at) return false;
+    t = s.clock_in[0];
+    c_old = s.clock_in[1];
+    const double smax = s.red_in[0];
+    c_new = c_old;
+    if (p.retarget_every > 0 && ((s.n % p.retarget_every) == 0 || smax > c_old)) c_new = smax / p.cfl;
+    dt = p.dx / c_new;
+    if (s.t_end < HUGE_VAL && t + dt >= s.t_end * (1.0 - 1e-14)) {
+        dt = s.t_end - t;
+        c_new = p.dx / dt;
+        last = true;
+    }
+    return true;
+}
+
+__device__ __forceinline__ void write_clock(const KStep& s, double t, double dt, double c_new, bool last)
+{
+    if (s.frozen) return;
+    s.clock_out[0] = last ? s.t_end : t + dt;
+    s.clock_out[1] = c_new;
+    if (last) atomicMin(s.stop_at, (unsigned long long)(s.n + 1));
+    if (s.red_clear)
+        for (int j = 0; j < 6; ++j) s.red_clear[j] = 0.0;
+}
+
+// Max of non-negative doubles through their IEEE bit patterns (monotone as
+// unsigned integers); NaNs dominate.
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v)
+{
+    atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_or(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Publish the per-lane maxima of one wave: s_max and M_k (nk of them), plus
+// the error bits.  Call with the whole wave active.
+__device__ __forceinline__ void wave_publish(const KStep& s, double smax, const double* M, int nk, int errbits)
+{
+    smax = wave_max(smax);
+    double Mr[4];
+    for (int k = 0; k < nk; ++k) Mr[k] = wave_max(M[k]);
+    errbits = wave_or(errbits);
+    if ((threadIdx.x & 63) == 0) {
+        atomic_max_nonneg(&s.red_out[0], smax);
+        for (int k = 0; k < nk; ++k) atomic_max_nonneg(&s.red_out[1 + k], Mr[k]);
+        if (errbits) {
+            atomicOr(s.err, errbits);
+            if (s.stop_at) atomicMin(s.stop_at, (unsigned long long)(s.n + 1));
+        }
+    }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Renumber them so that every XCD receives one contiguous range of logical
+// tiles: neighbouring tiles, which share halo cells, then share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int per = nb / 8, rem = nb % 8;
+    const int xcd = b % 8, idx = b / 8;
+    return xcd * per + min(xcd, rem) + idx;
+}
+
+__device__ __forceinline__ int wrap_index(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+}  // namespace vlbm

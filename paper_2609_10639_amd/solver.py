@@ -1,0 +1,179 @@
+"""Python face of the C ABI: a Solver owning one vlbm_ctx.
+
+Marshalling only: arrays go in and out as numpy (host) or torch (device)
+buffers, the stream is torch's current HIP stream, and every step of the
+method runs in the library's HIP kernels.
+"""
+import ctypes
+import math
+
+import numpy as np
+
+from . import _native as N
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Solver:
+    """VLBM solver on the current GPU.
+
+    Keyword arguments follow `vlbm_config` (include/vlbm.h): dim, nx, ny, dx,
+    bc (4-tuple), eos, gamma, vdw_a, vdw_b, vdw_R, cfl, retarget_every,
+    c_fixed, sensor, beta_const, beta_min, beta_max, c_sensor, eps_theta,
+    precision ("fp64" | "fp32").
+    """
+
+    DEFAULTS = dict(dim=1, nx=100, ny=1, dx=0.01, bc=(1, 1, 1, 1), eos=0, gamma=1.4, vdw_a=0.0, vdw_b=0.0,
+                    vdw_R=1.0, cfl=0.5, retarget_every=1, c_fixed=0.0, sensor=3, beta_const=1.0, beta_min=0.75,
+                    beta_max=1.0, c_sensor=4.0, eps_theta=1e-12, precision="fp64")
+
+    def __init__(self, stream=None, **kw):
+        torch = _torch()
+        d = dict(self.DEFAULTS)
+        d.update(kw)
+        self.params = d
+        cfg = N.VlbmConfig()
+        for k, v in d.items():
+            if k == "bc":
+                for j in range(4):
+                    cfg.bc[j] = int(v[j])
+            elif k == "precision":
+                cfg.precision = N.FP32 if v in ("fp32", N.FP32) else N.FP64
+            else:
+                setattr(cfg, k, v)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        cfg.stream = ctypes.c_void_p(stream.cuda_stream)
+        self.cfg = cfg
+        self.D = d["dim"]
+        self.NK = self.D + 2
+        self.Q = 2 * self.D
+        self.shape = (d["ny"], d["nx"])
+        self.fp32 = cfg.precision == N.FP32
+        h = ctypes.c_void_p()
+        st = N.lib().vlbm_create(ctypes.byref(cfg), ctypes.byref(h))
+        if st != N.OK:
+            raise N.VlbmError(st, "vlbm_create rejected the configuration")
+        self._h = h
+
+    # ------------------------------------------------------------ lifecycle
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            N.lib().vlbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        N.check(st, self._h)
+
+    # ------------------------------------------------------------ state
+    def init(self, W0):
+        """W0: numpy float64 (D+2, ny, nx) on the host, or a torch float64 device tensor."""
+        torch = _torch()
+        if isinstance(W0, torch.Tensor):
+            W0 = W0.to(dtype=torch.float64).contiguous()
+            assert W0.is_cuda and W0.numel() == self.NK * self.shape[0] * self.shape[1]
+            self._keep = W0
+            self._chk(N.lib().vlbm_init(self._h, ctypes.c_void_p(W0.data_ptr()), 1))
+        else:
+            W0 = np.ascontiguousarray(W0, dtype=np.float64)
+            assert W0.size == self.NK * self.shape[0] * self.shape[1]
+            self._chk(N.lib().vlbm_init(self._h, W0.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def step(self, nsteps=1, t_end_cap=math.inf):
+        n = ctypes.c_int64(0)
+        self._chk(N.lib().vlbm_step(self._h, int(nsteps), float(t_end_cap), ctypes.byref(n)))
+        return n.value
+
+    def run_to_time(self, t_end):
+        n = ctypes.c_int64(0)
+        self._chk(N.lib().vlbm_run_to_time(self._h, float(t_end), ctypes.byref(n)))
+        return n.value
+
+    def clock(self):
+        t, c, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        self._chk(N.lib().vlbm_get_clock(self._h, ctypes.byref(t), ctypes.byref(c), ctypes.byref(n)))
+        return t.value, c.value, n.value
+
+    def totals(self):
+        out = np.empty(self.NK)
+        self._chk(N.lib().vlbm_conserved_totals(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def W(self, device=False):
+        if device:
+            torch = _torch()
+            out = torch.empty((self.NK,) + self.shape, dtype=torch.float64, device="cuda")
+            self._chk(N.lib().vlbm_get_W(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        out = np.empty((self.NK,) + self.shape)
+        self._chk(N.lib().vlbm_get_W(self._h, out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
+
+    def beta(self):
+        out = np.empty(self.shape)
+        self._chk(N.lib().vlbm_get_beta(self._h, out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
+
+    def f(self):
+        out = np.empty((self.Q, self.NK) + self.shape, dtype=np.float32 if self.fp32 else np.float64)
+        self._chk(N.lib().vlbm_get_f(self._h, out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
+
+    def state_bytes(self):
+        return N.lib().vlbm_state_bytes(self._h)
+
+    def save(self):
+        """Checkpoint into a new uint8 device tensor."""
+        torch = _torch()
+        buf = torch.empty(self.state_bytes(), dtype=torch.uint8, device="cuda")
+        self._chk(N.lib().vlbm_save(self._h, ctypes.c_void_p(buf.data_ptr())))
+        return buf
+
+    def restore(self, buf):
+        self._chk(N.lib().vlbm_restore(self._h, ctypes.c_void_p(buf.data_ptr())))
+
+    # ------------------------------------------------------------ raw (frozen link speed)
+    def plane_elems(self):
+        return N.lib().vlbm_plane_elems(self._h)
+
+    def new_populations(self):
+        torch = _torch()
+        dt = torch.float32 if self.fp32 else torch.float64
+        return torch.empty((self.Q * self.NK, self.plane_elems()), dtype=dt, device="cuda")
+
+    def new_norms(self):
+        torch = _torch()
+        return torch.zeros(self.D + 3, dtype=torch.float64, device="cuda")
+
+    def raw_init(self, W0, f0, norms0):
+        self._chk(N.lib().vlbm_raw_init(self._h, _ptr(W0), _ptr(f0), _ptr(norms0)))
+
+    def raw_step(self, f_in, norms_in, f_out, norms_out):
+        self._chk(N.lib().vlbm_raw_step(self._h, _ptr(f_in), _ptr(norms_in), _ptr(f_out), _ptr(norms_out)))
+
+    def raw_adjoint_step(self, f_n, norms_n, lam_np1, lam_n):
+        self._chk(N.lib().vlbm_raw_adjoint_step(self._h, _ptr(f_n), _ptr(norms_n), _ptr(lam_np1), _ptr(lam_n)))
+
+    def raw_init_adjoint(self, W0, lam0, W0bar):
+        self._chk(N.lib().vlbm_raw_init_adjoint(self._h, _ptr(W0), _ptr(lam0), _ptr(W0bar)))
+
+    def raw_moments(self, f, W):
+        self._chk(N.lib().vlbm_raw_moments(self._h, _ptr(f), _ptr(W)))
+
+    def raw_moments_adjoint(self, Wbar, lam):
+        self._chk(N.lib().vlbm_raw_moments_adjoint(self._h, _ptr(Wbar), _ptr(lam)))
+
+
+def _ptr(t):
+    assert t.is_cuda and t.is_contiguous()
+    return ctypes.c_void_p(t.data_ptr())

@@ -1,0 +1,51 @@
+"""Shared test helpers: run the oracle and the GPU library on the same inputs."""
+import numpy as np
+
+from oracle import core
+from paper_2609_10639_amd import problems as pr
+
+# workloads: (builder, config) pairs with the paper's boundary and sensor choices
+IDEAL = pr.IDEAL_AIR.config()
+VDW = pr.VDW_REDUCED_CV50.config()
+
+
+def sod_case(n=1000):
+    W0, dx = pr.sod(n)
+    return W0, dict(dim=1, nx=n, ny=1, dx=dx, bc=(1, 1, 1, 1), cfl=0.5, sensor=1, **pr.SENSOR_1D, **IDEAL), 0.2
+
+
+def bzt1d_case(n=1024):
+    W0, dx = pr.bzt_tube(n)
+    return W0, dict(dim=1, nx=n, ny=1, dx=dx, bc=(1, 1, 1, 1), cfl=0.5, sensor=1, **pr.SENSOR_1D, **VDW), 0.2
+
+
+def vortex_case(n=128):
+    W0, dx = pr.vortex(n)
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D, **IDEAL), 10.0
+
+
+def riemann_case(n=128, config=3):
+    W0, dx = pr.riemann2d(n, config)
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2, **pr.SENSOR_2D, **IDEAL), 0.25
+
+
+def bzt2d_case(n=256):
+    W0, dx = pr.bzt_extrusion(n)
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D, **VDW), 0.2
+
+
+def oracle_for(cfg, W0):
+    kw = {k: v for k, v in cfg.items() if k != "precision"}
+    o = core.Oracle(**kw)
+    o.init(W0)
+    return o
+
+
+def rel_errors(a, b):
+    """Per-field relative Linf and relative L1 of a against reference b."""
+    out = []
+    for k in range(b.shape[0]):
+        d = np.abs(a[k] - b[k])
+        ref = np.abs(b[k])
+        out.append((d.max() / max(ref.max(), 1e-300), d.sum() / max(ref.sum(), 1e-300)))
+    return out

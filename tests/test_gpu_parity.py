@@ -1,0 +1,277 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+identical seeded inputs.
+
+Tolerances (per field, W components):
+  FP64 GPU vs oracle  relative Linf <= 1e-11 on smooth flows, relative L1 <= 1e-9
+                      on shocked flows (only rounding order and FMA contraction differ);
+  FP32 GPU vs oracle  relative Linf <= 1e-5 on smooth flows, relative L1 <= 1e-5
+                      on shocked flows (the target precision of the FP32 form).
+Step counts and the landing time must match exactly.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import (bzt1d_case, bzt2d_case, oracle_for, rel_errors, riemann_case, sod_case, vortex_case)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _solver(cfg, precision="fp64"):
+    import torch
+    from paper_2609_10639_amd import Solver
+    assert torch.cuda.is_available()
+    return Solver(precision=precision, **cfg)
+
+
+def _run_both(W0, cfg, t_end, precision="fp64"):
+    _say("case", cfg["dim"], cfg["nx"], cfg["ny"], precision, "t_end", t_end)
+    o = oracle_for(cfg, W0)
+    n_o = o.run_to_time(t_end)
+    s = _solver(cfg, precision)
+    s.init(W0)
+    n_g = s.run_to_time(t_end)
+    return o, n_o, s, n_g
+
+
+def _check(o, n_o, s, n_g, t_end, tol, norm):
+    assert s.clock()[0] == t_end and o.clock()[0] == t_end
+    assert n_g == n_o, (n_g, n_o)
+    errs = rel_errors(s.W(), o.W())
+    _say("steps", n_g, "errors (relLinf, relL1) per field:", ["%.2e/%.2e" % e for e in errs])
+    idx = 0 if norm == "linf" else 1
+    for k, e in enumerate(errs):
+        assert e[idx] <= tol, (k, e)
+
+
+# ------------------------------------------------------------------ FP64 parity
+
+
+def test_sod_fp64():
+    W0, cfg, t_end = sod_case(1000)
+    o, n_o, s, n_g = _run_both(W0, cfg, t_end)
+    _check(o, n_o, s, n_g, t_end, 1e-9, "l1")
+
+
+def test_bzt_tube_fp64():
+    W0, cfg, t_end = bzt1d_case(1024)
+    o, n_o, s, n_g = _run_both(W0, cfg, t_end)
+    _check(o, n_o, s, n_g, t_end, 1e-9, "l1")
+
+
+def test_vortex_fp64():
+    W0, cfg, t_end = vortex_case(128)
+    o, n_o, s, n_g = _run_both(W0, cfg, t_end)
+    _check(o, n_o, s, n_g, t_end, 1e-11, "linf")
+
+
+@pytest.mark.parametrize("config", [3, 12])
+def test_riemann_fp64(config):
+    W0, cfg, t_end = riemann_case(128, config)
+    o, n_o, s, n_g = _run_both(W0, cfg, t_end)
+    _check(o, n_o, s, n_g, t_end, 1e-9, "l1")
+
+
+def test_bzt_extrusion_fp64():
+    W0, cfg, _ = bzt2d_case(128)
+    o, n_o, s, n_g = _run_both(W0, cfg, 0.05)
+    _check(o, n_o, s, n_g, 0.05, 1e-9, "l1")
+
+
+@pytest.mark.parametrize("shape,bc", [((67, 130), (0, 0, 0, 0)), ((67, 130), (1, 1, 1, 1)),
+                                      ((5, 7), (1, 1, 0, 0)), ((61, 4), (0, 0, 1, 1)), ((59, 117), (1, 1, 0, 0))])
+def test_ragged_grids_fp64(shape, bc):
+    ny, nx = shape
+    from paper_2609_10639_amd import problems as pr
+    W = pr.random_admissible_state(2, shape, seed=nx * 1000 + ny, u_amp=0.3)
+    cfg = dict(dim=2, nx=nx, ny=ny, dx=1.0 / nx, bc=bc, cfl=0.45, sensor=2, **pr.SENSOR_2D, **pr.IDEAL_AIR.config())
+    o, n_o, s, n_g = _run_both(W, cfg, 0.02)
+    _check(o, n_o, s, n_g, 0.02, 1e-9, "l1")
+
+
+@pytest.mark.parametrize("sensor", [0, 1, 2])
+def test_sensor_modes_and_beta_diagnostic(sensor):
+    W0, cfg, _ = riemann_case(96, 12)
+    cfg = dict(cfg, sensor=sensor, beta_const=0.8)
+    o = oracle_for(cfg, W0)
+    s = _solver(cfg)
+    s.init(W0)
+    for _ in range(3):
+        o.step()
+    s.step(3)
+    bo, bg = o.beta(), s.beta()
+    _say("sensor", sensor, "beta max diff", np.abs(bo - bg).max())
+    assert np.abs(bo - bg).max() <= 1e-12
+    errs = rel_errors(s.W(), o.W())
+    assert max(e[0] for e in errs) <= 1e-12
+
+
+def test_retarget_every_k_and_frozen_speed():
+    W0, cfg, _ = sod_case(400)
+    for kw in (dict(retarget_every=7), dict(retarget_every=0, c_fixed=6.0)):
+        c = dict(cfg, **kw)
+        o = oracle_for(c, W0)
+        s = _solver(c)
+        s.init(W0)
+        for _ in range(40):
+            o.step()
+        s.step(40)
+        assert abs(s.clock()[1] - o.clock()[1]) <= 1e-12 * o.clock()[1]
+        errs = rel_errors(s.W(), o.W())
+        assert max(e[1] for e in errs) <= 1e-11
+
+
+# ------------------------------------------------------------------ FP32 form
+
+
+def test_vortex_fp32():
+    W0, cfg, t_end = vortex_case(128)
+    o, n_o, s, n_g = _run_both(W0, cfg, t_end, "fp32")
+    assert s.clock()[0] == t_end
+    assert abs(n_g - n_o) <= 1
+    errs = rel_errors(s.W(), o.W())
+    _say("fp32 vortex", ["%.2e/%.2e" % e for e in errs])
+    for e in errs:
+        assert e[0] <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["riemann3", "riemann12", "sod", "bzt1d"])
+def test_shocked_fp32(case):
+    W0, cfg, t_end = {"riemann3": lambda: riemann_case(128, 3), "riemann12": lambda: riemann_case(128, 12),
+                      "sod": lambda: sod_case(1000), "bzt1d": lambda: bzt1d_case(1024)}[case]()
+    o, n_o, s, n_g = _run_both(W0, cfg, t_end, "fp32")
+    assert s.clock()[0] == t_end
+    errs = rel_errors(s.W(), o.W())
+    _say("fp32", case, "steps", n_g, n_o, ["%.2e/%.2e" % e for e in errs])
+    for e in errs:
+        assert e[1] <= 1e-5
+
+
+# ------------------------------------------------------------------ invariants
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_conservation_periodic(precision):
+    W0, cfg, _ = vortex_case(128)
+    s = _solver(cfg, precision)
+    s.init(W0)
+    tot0 = s.totals()
+    o = oracle_for(cfg, W0)
+    assert np.allclose(tot0, o.totals(), rtol=1e-7 if precision == "fp32" else 1e-14, atol=1e-12)
+    drift = []
+    for _ in range(10):
+        s.step(20)
+        drift.append(np.abs(s.totals() - tot0) / np.abs(W0).sum(axis=(1, 2)).max() * W0[0].size)
+    worst = np.max(drift)
+    _say(precision, "relative drift of totals over 200 steps", worst)
+    assert worst <= (1e-6 if precision == "fp32" else 1e-13)
+
+
+def test_tilings_agree_bitwise(monkeypatch):
+    W0, cfg, _ = riemann_case(200, 3)
+    outs = []
+    for h in ("16", "37", "200"):
+        monkeypatch.setenv("VLBM_SEG_H", h)
+        s = _solver(cfg)
+        s.init(W0)
+        s.step(30)
+        outs.append(s.f())
+        s.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_deterministic_repeat():
+    W0, cfg, _ = riemann_case(128, 3)
+    res = []
+    for _ in range(2):
+        s = _solver(cfg)
+        s.init(W0)
+        s.step(50)
+        res.append((s.f(), s.totals(), s.clock()))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    assert res[0][2] == res[1][2]
+
+
+def test_save_restore_bitwise():
+    W0, cfg, _ = riemann_case(128, 12)
+    s = _solver(cfg)
+    s.init(W0)
+    s.step(10)
+    buf = s.save()
+    s.step(25)
+    ref_f, ref_clock = s.f(), s.clock()
+    s.restore(buf)
+    s.step(25)
+    assert np.array_equal(s.f(), ref_f) and s.clock() == ref_clock
+
+
+def test_inadmissible_states_are_reported():
+    from paper_2609_10639_amd import _native as N
+    W0, cfg, _ = sod_case(200)
+    bad = W0.copy()
+    bad[2, 0, 50] = 0.0   # negative internal energy -> negative pressure
+    s = _solver(cfg)
+    with pytest.raises(N.VlbmError) as e:
+        s.init(bad)
+    assert e.value.status == N.ENONHYPERBOLIC
+    nan = W0.copy()
+    nan[0, 0, 10] = np.nan
+    with pytest.raises(N.VlbmError) as e:
+        s.init(nan)
+    assert e.value.status in (N.ENONFINITE, N.ENONHYPERBOLIC)
+    # an admissible state that becomes inadmissible: the four-quadrant all-shock
+    # problem with the 1-D sensor constants loses positivity within a few steps
+    W0, cfg, _ = riemann_case(64, 3)
+    cfg = dict(cfg, beta_min=0.75, c_sensor=4.0)
+    s = _solver(cfg)
+    s.init(W0)
+    with pytest.raises(N.VlbmError) as e:
+        s.run_to_time(0.25)
+    assert e.value.status in (N.ENONHYPERBOLIC, N.ENONFINITE)
+    t, c, n = s.clock()
+    assert 0 < n < 10
+
+
+def test_bad_configs_rejected():
+    from paper_2609_10639_amd import _native as N
+    W0, cfg, _ = sod_case(100)
+    for bad in (dict(cfl=0.0), dict(bc=(0, 1, 1, 1)), dict(nx=2), dict(beta_min=1.2), dict(dim=3),
+                dict(retarget_every=0, c_fixed=0.0)):
+        with pytest.raises(N.VlbmError):
+            _solver(dict(cfg, **bad))
+
+
+# ------------------------------------------------------------------ full-size configurations
+
+
+@pytest.mark.parametrize("name,precision,steps", [("vortex1024", "fp64", 4), ("vortex1024", "fp32", 4),
+                                                  ("riemann4096", "fp32", 2), ("bzt2048", "fp32", 3),
+                                                  ("bzt8192", "fp64", 40)])
+def test_full_size_against_oracle(name, precision, steps):
+    """At the benchmark sizes and launch configuration: a few steps compared
+    with the oracle over the whole grid."""
+    case = {"vortex1024": lambda: vortex_case(1024), "riemann4096": lambda: riemann_case(4096, 3),
+            "bzt2048": lambda: bzt2d_case(2048), "bzt8192": lambda: bzt1d_case(8192)}[name]
+    W0, cfg, _ = case()
+    _say("full size", name, precision, steps)
+    o = oracle_for(cfg, W0)
+    for _ in range(steps):
+        o.step()
+    s = _solver(cfg, precision)
+    s.init(W0)
+    s.step(steps)
+    assert s.clock()[2] == steps
+    assert abs(s.clock()[0] - o.clock()[0]) <= 1e-12 * o.clock()[0]
+    errs = rel_errors(s.W(), o.W())
+    _say(" errors", ["%.2e/%.2e" % e for e in errs])
+    tol = 1e-11 if precision == "fp64" else 1e-5
+    for e in errs:
+        assert e[0] <= tol * 10 and e[1] <= tol
