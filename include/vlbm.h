@@ -60,7 +60,9 @@ typedef enum {
 enum { VLBM_BC_PERIODIC = 0, VLBM_BC_OUTFLOW = 1 };
 enum { VLBM_EOS_IDEAL = 0, VLBM_EOS_VDW = 1 };
 enum { VLBM_SENSOR_OFF = 0, VLBM_SENSOR_A = 1, VLBM_SENSOR_B = 2, VLBM_SENSOR_AUTO = 3 };
-enum { VLBM_FP64 = 0, VLBM_FP32 = 1 };
+/* precision of a context: FP64 populations and arithmetic; FP32 populations
+ * and arithmetic; FP32 populations in HBM with FP64 arithmetic in registers */
+enum { VLBM_FP64 = 0, VLBM_FP32 = 1, VLBM_FP32_MIXED = 2 };
 
 /* Problem statement (Sec. II-III): lattice, grid, boundaries, EOS, time
  * stepping and sensor constants. */
@@ -79,8 +81,8 @@ typedef struct {
     double c_fixed;          /* link speed when retarget_every == 0 */
     int32_t sensor;          /* VLBM_SENSOR_*: OFF uses beta_const; A = Eq. 34; B = Eq. 35 */
     double beta_const, beta_min, beta_max, c_sensor, eps_theta;
-    int32_t precision;       /* VLBM_FP64 or VLBM_FP32 (populations and per-cell arithmetic;
-                                clock, dt reduction and totals stay FP64) */
+    int32_t precision;       /* VLBM_FP64, VLBM_FP32 or VLBM_FP32_MIXED (populations and per-cell
+                                arithmetic; clock, dt reduction and totals stay FP64) */
     void* stream;            /* hipStream_t, or NULL for the default stream */
 } vlbm_config;
 

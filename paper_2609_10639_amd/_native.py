@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONHYP
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 EOS_IDEAL, EOS_VDW = 0, 1
 SENSOR_OFF, SENSOR_A, SENSOR_B, SENSOR_AUTO = 0, 1, 2, 3
-FP64, FP32 = 0, 1
+FP64, FP32, FP32_MIXED = 0, 1, 2
 
 
 class VlbmConfig(ctypes.Structure):

@@ -2,8 +2,8 @@
 #include "vlbm_aux.hpp"
 namespace vlbm {
 size_t adjoint_partials_count(const KParams&) { return 1; }
-hipError_t launch_adjoint_step(const KParams&, bool, const void*, const double*, const void*, void*,
+hipError_t launch_adjoint_step(const KParams&, int, const void*, const double*, const void*, void*,
                                const AdjScratch&, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_init_adjoint(const KParams&, bool, const double*, long long, const void*, double*, hipStream_t)
+hipError_t launch_init_adjoint(const KParams&, int, const double*, long long, const void*, double*, hipStream_t)
 { return hipErrorNotSupported; }
 }

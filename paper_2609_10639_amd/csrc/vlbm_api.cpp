@@ -28,7 +28,8 @@ struct vlbm_ctx {
     vlbm_config cfg;
     KParams kp;
     int D, Q, NK, nplanes;
-    bool fp32;
+    int prec;      // PREC_*
+    bool fp32;     // populations stored as FP32
     size_t esize;
     long long ncell, plane;
     void* f[2] = {nullptr, nullptr};
@@ -78,7 +79,7 @@ vlbm_status err_status(int bits)
 
 // rows per segment of the D2Q4 march: enough wavefronts to fill every CU
 // once at the kernel's occupancy, without a partial second round
-int choose_seg_h(const KParams& p, bool fp32)
+int choose_seg_h(const KParams& p, int prec)
 {
     if (const char* env = getenv("VLBM_SEG_H")) {
         const int v = atoi(env);
@@ -90,7 +91,7 @@ int choose_seg_h(const KParams& p, bool fp32)
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
             cus = prop.multiProcessorCount;
     }
-    int per_cu = step_d2q4_blocks_per_cu(p, fp32);
+    int per_cu = step_d2q4_blocks_per_cu(p, prec);
     if (per_cu <= 0) per_cu = 8;
     const long long resident = (long long)cus * per_cu;
     long long nsegs = std::max(1LL, resident / p.nstrips);
@@ -126,8 +127,8 @@ hipError_t launch_one(vlbm_ctx* ctx, long long n, double t_end)
     s.t_end = t_end;
     const void* fin = ctx->f[n & 1];
     void* fout = ctx->f[(n + 1) & 1];
-    return ctx->D == 2 ? launch_step_d2q4(ctx->kp, s, ctx->fp32, fin, fout, ctx->stream)
-                       : launch_step_d1q2(ctx->kp, s, ctx->fp32, fin, fout, ctx->stream);
+    return ctx->D == 2 ? launch_step_d2q4(ctx->kp, s, ctx->prec, fin, fout, ctx->stream)
+                       : launch_step_d1q2(ctx->kp, s, ctx->prec, fin, fout, ctx->stream);
 }
 
 // launch `count` steps from the host's step index, read back, update the mirror
@@ -183,7 +184,8 @@ bool check_config(const vlbm_config* c, std::string& why)
         (!okb(c->beta_min) || !okb(c->beta_max) || c->beta_min > c->beta_max || !(c->c_sensor >= 0) ||
          !(c->eps_theta > 0)))
         return why = "bad sensor constants", false;
-    if (c->precision != VLBM_FP64 && c->precision != VLBM_FP32) return why = "bad precision", false;
+    if (c->precision != VLBM_FP64 && c->precision != VLBM_FP32 && c->precision != VLBM_FP32_MIXED)
+        return why = "bad precision", false;
     return true;
 }
 
@@ -207,7 +209,8 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
     ctx->Q = 2 * cfg->dim;
     ctx->NK = cfg->dim + 2;
     ctx->nplanes = ctx->Q * ctx->NK;
-    ctx->fp32 = cfg->precision == VLBM_FP32;
+    ctx->prec = cfg->precision == VLBM_FP32 ? PREC_FP32 : cfg->precision == VLBM_FP32_MIXED ? PREC_FP32_MIXED : PREC_FP64;
+    ctx->fp32 = ctx->prec != PREC_FP64;
     ctx->esize = ctx->fp32 ? 4 : 8;
     ctx->ncell = cfg->nx * cfg->ny;
     ctx->plane = (ctx->ncell + 63) / 64 * 64;
@@ -237,11 +240,17 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
     p.beta_max = cfg->beta_max;
     p.c_sensor = cfg->c_sensor;
     p.eps_theta = cfg->eps_theta;
-    p.nstrips = (p.nx + 57) / 58;
+    // D2Q4 strips own whole 128-byte lines of every plane row
+    p.strip_w = ctx->fp32 ? 32 : 48;
+    if (const char* env = getenv("VLBM_STRIP_W")) {
+        const int v = atoi(env);
+        if (v >= 8 && v <= 58 && v % 2 == 0) p.strip_w = v;
+    }
+    p.nstrips = (p.nx + p.strip_w - 1) / p.strip_w;
     p.seg_h = p.ny;
     p.nsegs = 1;
     if (cfg->dim == 2) {
-        p.seg_h = choose_seg_h(p, ctx->fp32);
+        p.seg_h = choose_seg_h(p, ctx->prec);
         p.nsegs = (p.ny + p.seg_h - 1) / p.seg_h;
     }
 
@@ -400,8 +409,8 @@ vlbm_status vlbm_get_beta(vlbm_ctx* ctx, double* out, int32_t out_on_device)
     s.beta_out = out_on_device ? out : ctx->scratchB;
     s.t_end = HUGE_VAL;
     const void* fin = ctx->f[ctx->n & 1];
-    HIPCHK(ctx, ctx->D == 2 ? launch_step_d2q4(p, s, ctx->fp32, fin, nullptr, ctx->stream)
-                            : launch_step_d1q2(p, s, ctx->fp32, fin, nullptr, ctx->stream));
+    HIPCHK(ctx, ctx->D == 2 ? launch_step_d2q4(p, s, ctx->prec, fin, nullptr, ctx->stream)
+                            : launch_step_d1q2(p, s, ctx->prec, fin, nullptr, ctx->stream));
     if (!out_on_device)
         HIPCHK(ctx, hipMemcpyAsync(out, ctx->scratchB, (size_t)ctx->ncell * sizeof(double), hipMemcpyDeviceToHost,
                                    ctx->stream));
@@ -518,8 +527,8 @@ vlbm_status vlbm_raw_step(vlbm_ctx* ctx, const void* f_in, const double* norms_i
     s.err = ctx->raw_err;
     s.frozen = 1;
     s.t_end = HUGE_VAL;
-    HIPCHK(ctx, ctx->D == 2 ? launch_step_d2q4(ctx->kp, s, ctx->fp32, f_in, f_out, ctx->stream)
-                            : launch_step_d1q2(ctx->kp, s, ctx->fp32, f_in, f_out, ctx->stream));
+    HIPCHK(ctx, ctx->D == 2 ? launch_step_d2q4(ctx->kp, s, ctx->prec, f_in, f_out, ctx->stream)
+                            : launch_step_d1q2(ctx->kp, s, ctx->prec, f_in, f_out, ctx->stream));
     return VLBM_OK;
 }
 
@@ -529,7 +538,7 @@ vlbm_status vlbm_raw_adjoint_step(vlbm_ctx* ctx, const void* f_n, const double* 
     if (vlbm_status st = need_frozen(ctx)) return st;
     if (!f_n || !norms_n || !lam_np1 || !lam_n) return fail(ctx, VLBM_EINVAL, "null argument");
     if (lam_np1 == lam_n) return fail(ctx, VLBM_EINVAL, "lam_np1 and lam_n must differ");
-    HIPCHK(ctx, launch_adjoint_step(ctx->kp, ctx->fp32, f_n, norms_n, lam_np1, lam_n, ctx->adj, ctx->stream));
+    HIPCHK(ctx, launch_adjoint_step(ctx->kp, ctx->prec, f_n, norms_n, lam_np1, lam_n, ctx->adj, ctx->stream));
     return VLBM_OK;
 }
 
@@ -537,7 +546,7 @@ vlbm_status vlbm_raw_init_adjoint(vlbm_ctx* ctx, const double* W0, const void* l
 {
     if (vlbm_status st = need_frozen(ctx)) return st;
     if (!W0 || !lam0 || !W0bar) return fail(ctx, VLBM_EINVAL, "null argument");
-    HIPCHK(ctx, launch_init_adjoint(ctx->kp, ctx->fp32, W0, ctx->ncell, lam0, W0bar, ctx->stream));
+    HIPCHK(ctx, launch_init_adjoint(ctx->kp, ctx->prec, W0, ctx->ncell, lam0, W0bar, ctx->stream));
     return VLBM_OK;
 }
 

@@ -5,11 +5,9 @@
 
 namespace vlbm {
 
-hipError_t launch_step_d2q4(const KParams& p, const KStep& s, bool fp32, const void* fin, void* fout,
-                            hipStream_t st);
-hipError_t launch_step_d1q2(const KParams& p, const KStep& s, bool fp32, const void* fin, void* fout,
-                            hipStream_t st);
-int step_d2q4_blocks_per_cu(const KParams& p, bool fp32);
+hipError_t launch_step_d2q4(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st);
+hipError_t launch_step_d1q2(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st);
+int step_d2q4_blocks_per_cu(const KParams& p, int prec);
 
 hipError_t launch_reset_ctl(double* ring, unsigned long long* stop_at, int* err, hipStream_t st);
 hipError_t launch_reset_stop(unsigned long long* stop_at, int* err, hipStream_t st);
@@ -37,9 +35,9 @@ struct AdjScratch {
     int* err;
 };
 size_t adjoint_partials_count(const KParams& p);
-hipError_t launch_adjoint_step(const KParams& p, bool fp32, const void* f_n, const double* norms_n,
+hipError_t launch_adjoint_step(const KParams& p, int prec, const void* f_n, const double* norms_n,
                                const void* lam_np1, void* lam_n, const AdjScratch& sc, hipStream_t st);
-hipError_t launch_init_adjoint(const KParams& p, bool fp32, const double* W0, long long ncell, const void* lam0,
+hipError_t launch_init_adjoint(const KParams& p, int prec, const double* W0, long long ncell, const void* lam0,
                                double* W0bar, hipStream_t st);
 
 }  // namespace vlbm

@@ -19,6 +19,7 @@ struct KParams {
     int retarget_every;
     int sensor;               // resolved: 0 off, 1 A (no gate), 2 B (Ducros gate)
     double beta_const, beta_min, beta_max, c_sensor, eps_theta;
+    int strip_w;              // D2Q4: output columns per wavefront (a whole number of 128-byte lines)
     int nstrips, seg_h, nsegs; // D2Q4 tiling: strips of columns x segments of rows
 };
 
@@ -43,10 +44,44 @@ struct KStep {
     double* beta_out;              // probe output, FP64 (ny, nx)
 };
 
+// population storage / arithmetic precision of a context
+constexpr int PREC_FP64 = 0;        // FP64 populations, FP64 arithmetic
+constexpr int PREC_FP32 = 1;        // FP32 populations, FP32 arithmetic
+constexpr int PREC_FP32_MIXED = 2;  // FP32 populations, FP64 arithmetic
+
 constexpr int ERR_NONHYP = 1;
 constexpr int ERR_NONFINITE = 2;
 
 // ------------------------------------------------------------- device helpers
+
+// Reciprocal from the hardware estimate refined by Newton-Raphson steps
+// (e = 1 - x r, r <- r + r e): two steps in FP64 bring it to within about an
+// ulp of the correctly rounded quotient; in FP32 the estimate (1 ulp) is used.
+__device__ __forceinline__ double fast_rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Square root of x >= 0 (0 for x <= 0): FP64 from the reciprocal square-root
+// estimate with Newton-Raphson refinement of s = x/sqrt(x) and h = 1/(2 sqrt(x));
+// FP32 from the hardware square root (1 ulp).
+__device__ __forceinline__ double fast_sqrt(double x)
+{
+    if (!(x > 0.0)) return 0.0;
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+__device__ __forceinline__ float fast_sqrt(float x) { return x > 0.0f ? __builtin_amdgcn_sqrtf(x) : 0.0f; }
 
 template <typename T>
 struct Gas {
@@ -75,7 +110,7 @@ __device__ __forceinline__ T eos_pressure(const Gas<T>& g, T rho, T e)
         return g.gm1 * rho * e;
     } else {
         const T temp = (e + g.a * rho) * g.inv_cv;
-        return g.R * rho * temp / ((T)1 - g.b * rho) - g.a * rho * rho;
+        return g.R * rho * temp * fast_rcp((T)1 - g.b * rho) - g.a * rho * rho;
     }
 }
 
@@ -89,7 +124,7 @@ __device__ __forceinline__ T eos_cs2(const Gas<T>& g, T rho, T e)
     } else {
         const T temp = (e + g.a * rho) * g.inv_cv;
         const T d = (T)1 - g.b * rho;
-        return g.gamma * g.R * temp / (d * d) - (T)2 * g.a * rho;
+        return g.gamma * g.R * temp * fast_rcp(d * d) - (T)2 * g.a * rho;
     }
 }
 

@@ -16,11 +16,11 @@ constexpr int kTile1 = 256;
 constexpr int kHalo1 = 3;
 constexpr int kSlots1 = kTile1 + 2 * kHalo1;
 
-template <typename T, int EOS, int SENSOR>
-__global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep S, const T* __restrict__ fin,
-                                                   T* __restrict__ fout)
+template <typename ST, typename T, int EOS, int SENSOR>
+__global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep S, const ST* __restrict__ fin,
+                                                   ST* __restrict__ fout)
 {
-    __shared__ T sf[6][kSlots1];   // reprojected populations, plane i*3+k
+    __shared__ T sf[6][kSlots1];   // reprojected populations, plane i*3+k (arithmetic type)
     __shared__ T sq[3][kSlots1];   // flux Q_k
     __shared__ T sa[kSlots1];      // activity s
     __shared__ T sg[6][kSlots1];   // post-collision populations
@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
         const int cx = cell_of(x0 - kHalo1 + s);
         T f[6];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) f[j] = fin[j * plane + cx];
+        for (int j = 0; j < 6; ++j) f[j] = (T)fin[j * plane + cx];
         if (reproj) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
                 gn[3 + k] = sg[3 + k][sr];
             }
 #pragma unroll
-            for (int j = 0; j < 6; ++j) fout[j * plane + X] = gn[j];
+            for (int j = 0; j < 6; ++j) fout[j * plane + X] = (ST)gn[j];
             const T rho = gn[0] + gn[3], m = gn[1] + gn[4], E = gn[2] + gn[5];
             const T u = m / rho;
             const T e = E / rho - (T)0.5 * u * u;
@@ -151,26 +151,30 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
     wave_publish(S, red_s, red_M, 3, errbits);
 }
 
-template <typename T>
+template <typename ST, typename T>
 static hipError_t launch_t(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
 {
     const dim3 grid((p.nx + kTile1 - 1) / kTile1), block(kTile1);
-    const T* in = (const T*)fin;
-    T* out = (T*)fout;
-#define VLBM_CASE(E, SN)                                                                  \
-    if (p.eos == E && p.sensor == SN) {                                                   \
-        hipLaunchKernelGGL((k_step_d1q2<T, E, SN>), grid, block, 0, st, p, s, in, out); \
-        return hipGetLastError();                                                         \
+    const ST* in = (const ST*)fin;
+    ST* out = (ST*)fout;
+#define VLBM_CASE(E, SN)                                                                      \
+    if (p.eos == E && p.sensor == SN) {                                                       \
+        hipLaunchKernelGGL((k_step_d1q2<ST, T, E, SN>), grid, block, 0, st, p, s, in, out); \
+        return hipGetLastError();                                                             \
     }
     VLBM_CASE(0, 0) VLBM_CASE(0, 1) VLBM_CASE(1, 0) VLBM_CASE(1, 1)
 #undef VLBM_CASE
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_step_d1q2(const KParams& p, const KStep& s, bool fp32, const void* fin, void* fout,
-                            hipStream_t st)
+hipError_t launch_step_d1q2(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st)
 {
-    return fp32 ? launch_t<float>(p, s, fin, fout, st) : launch_t<double>(p, s, fin, fout, st);
+    switch (prec) {
+    case PREC_FP64: return launch_t<double, double>(p, s, fin, fout, st);
+    case PREC_FP32: return launch_t<float, float>(p, s, fin, fout, st);
+    case PREC_FP32_MIXED: return launch_t<float, double>(p, s, fin, fout, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace vlbm

@@ -1,28 +1,37 @@
 // Fused D2Q4 VLBM time step for gfx950 (arXiv 2609.10639, Sec. III).
 //
-// One wavefront owns a strip of 58 output columns and marches up a segment of
-// rows.  Its 64 lanes hold 64 consecutive columns (3 halo columns on each
-// side); x-neighbour values move between lanes through the LDS crossbar
-// (ds_bpermute), y-neighbour values are the previous rows kept in registers.
-// For the row R entering the strip the pipeline runs, within one iteration:
-//   A  row R    load the 16 populations (SoA planes, coalesced), reproject to
-//               the new link speed (Eqs. 38-40), moments W, primitives, EOS
-//               pressure, flux Q_x, Q_y (Eq. 10), x-parts of the central
-//               differences of Q and u;
+// One wavefront owns a strip of output columns and marches up a segment of
+// rows.  The strip is a whole number of 128-byte lines (48 FP64 or 32 FP32
+// columns, aligned), so that every store fills complete L2 lines: partially
+// written lines cost HBM bandwidth far beyond their size.  The 64 lanes hold
+// 64 consecutive columns centred on the strip (the stencil needs 3 halo
+// columns on each side); x-neighbour values move between lanes through the LDS crossbar
+// (ds_bpermute); the raw populations of the last three rows sit in a per-wave
+// LDS ring; the per-row partial sums that later rows complete sit in
+// registers.  The march is unrolled by three so that every row slot (LDS ring
+// and register histories alike) is a compile-time index.
+//
+// Iteration R (front row R) runs, in this order:
+//   issue the global loads of row R (they stay in flight during stage C);
+//   C  row R-3  y-pass of the box filter, beta (Eqs. 34-35), reprojection to
+//               the new link speed (Eqs. 38-40) of the populations read back
+//               from LDS, over-relaxation towards the vector equilibrium
+//               (Eqs. 20, 22), streaming (Eq. 21) as stores into the rows
+//               R-4..R-2 of the new populations, and the reductions of the
+//               new state (s_max of Eq. 36, M_k of Eq. 30) for the next step;
+//   A  row R    moments W (of the un-reprojected populations: reprojection
+//               leaves W unchanged), primitives, EOS pressure, flux (Eq. 10),
+//               x-parts of the central differences of Q and u, completion of
+//               the y-differences of row R-1; the raw row is parked in LDS;
 //   B  row R-1  flux-divergence jump j_k (Eqs. 28-29), normalised activity s
-//               (Eqs. 30-31), Ducros ratio theta (Eqs. 32-33), x-pass of the box filter;
-//   C  row R-2  y-pass of the box filter, beta (Eqs. 34-35), over-relaxation
-//               towards the vector equilibrium (Eqs. 20, 22);
-//   D  row R-3  pull-streaming (Eq. 21) of the four directions into the new
-//               populations, store, and the reductions of the new state
-//               (s_max of Eq. 36, M_k of Eq. 30) that the next step needs.
-// Every population is read once and written once per step; halo rows and
-// columns are re-read from L2.
+//               (Eqs. 30-31), Ducros ratio theta (Eqs. 32-33), x-pass of the
+//               box filter.
+// Every population is read once from HBM and written once; halo rows and
+// columns are re-read through L2.  S is the storage type of the populations,
+// C the arithmetic type.
 #include "vlbm_common.hpp"
 
 namespace vlbm {
-
-constexpr int kStripW = 58;  // output columns per wavefront (64 lanes - 2*3 halo)
 
 template <typename T>
 __device__ __forceinline__ T shfl(T v, int src)
@@ -30,38 +39,59 @@ __device__ __forceinline__ T shfl(T v, int src)
     return __shfl(v, src, 64);
 }
 
-template <typename T>
-__device__ __forceinline__ void reproject4(T* f, T r)
+// Buffer addressing of the population arrays: one resource per group of four
+// planes (base in SGPRs), the plane offset within the group in the scalar
+// offset and the cell's byte offset as the only per-lane operand, so that no
+// per-lane 64-bit address arithmetic is spent on the 32 loads and stores of a row.
+struct Planes {
+    __amdgpu_buffer_rsrc_t rs[4];
+    unsigned plane_bytes;
+};
+
+template <typename S>
+__device__ __forceinline__ Planes make_planes(const S* base, unsigned plane)
 {
-    // Eq. 40 with J_alpha = c_old (f_alpha+ - f_alpha-) and K = c_old^2 (S_x - S_y)
-    // held fixed, in terms of r = c_old/c_new, for each component k.
+    Planes p;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const T sx = f[0 * 4 + k] + f[1 * 4 + k], dxv = f[0 * 4 + k] - f[1 * 4 + k];
-        const T sy = f[2 * 4 + k] + f[3 * 4 + k], dyv = f[2 * 4 + k] - f[3 * 4 + k];
-        const T w = sx + sy;
-        const T kk = r * r * (sx - sy);
-        const T a = (T)0.25 * (w + kk), b = (T)0.25 * (w - kk);
-        const T hx = (T)0.5 * r * dxv, hy = (T)0.5 * r * dyv;
-        f[0 * 4 + k] = a + hx;
-        f[1 * 4 + k] = a - hx;
-        f[2 * 4 + k] = b + hy;
-        f[3 * 4 + k] = b - hy;
-    }
+    for (int g = 0; g < 4; ++g)
+        p.rs[g] = __builtin_amdgcn_make_buffer_rsrc((void*)(base + (size_t)4 * g * plane), (short)0, (int)0xffffffff,
+                                                    0x00020000);
+    p.plane_bytes = plane * (unsigned)sizeof(S);
+    return p;
 }
 
-// W, velocity, pressure and the two directional fluxes of one cell.
-template <typename T, int EOS>
-__device__ __forceinline__ void cell_flux(const Gas<T>& g, const T* f, T* W, T& ux, T& uy, T& e, T* qx, T* qy)
+__device__ __forceinline__ double bload(const Planes& p, int j, unsigned off, double)
+{
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(p.rs[j >> 2], off, (j & 3) * p.plane_bytes, 0);
+    return __builtin_bit_cast(double, v);
+}
+__device__ __forceinline__ float bload(const Planes& p, int j, unsigned off, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.rs[j >> 2], off, (j & 3) * p.plane_bytes, 0));
+}
+__device__ __forceinline__ void bstore(const Planes& p, int j, unsigned off, double v)
+{
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), p.rs[j >> 2], off, (j & 3) * p.plane_bytes, 0);
+}
+__device__ __forceinline__ void bstore(const Planes& p, int j, unsigned off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), p.rs[j >> 2], off, (j & 3) * p.plane_bytes, 0);
+}
+
+// W, velocity, internal energy, pressure and the two directional fluxes.
+template <typename C, int EOS>
+__device__ __forceinline__ void cell_flux(const Gas<C>& g, const C* f, C* W, C& ux, C& uy, C* qx, C* qy)
 {
 #pragma unroll
     for (int k = 0; k < 4; ++k) W[k] = (f[0 * 4 + k] + f[1 * 4 + k]) + (f[2 * 4 + k] + f[3 * 4 + k]);
-    const T irho = (T)1 / W[0];
+    const C irho = fast_rcp(W[0]);
     ux = W[1] * irho;
     uy = W[2] * irho;
-    e = W[3] * irho - (T)0.5 * (ux * ux + uy * uy);
-    const T P = eos_pressure<T, EOS>(g, W[0], e);
-    const T h = W[3] + P;
+    const C e = W[3] * irho - (C)0.5 * (ux * ux + uy * uy);
+    const C P = eos_pressure<C, EOS>(g, W[0], e);
+    const C h = W[3] + P;
     qx[0] = W[1];
     qx[1] = W[1] * ux + P;
     qx[2] = W[1] * uy;
@@ -72,263 +102,348 @@ __device__ __forceinline__ void cell_flux(const Gas<T>& g, const T* f, T* W, T& 
     qy[3] = h * uy;
 }
 
-template <typename T, int EOS, int SENSOR>
-__global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep S, const T* __restrict__ fin,
-                                                  T* __restrict__ fout)
+template <typename S, typename C, int EOS, int SENSOR>
+struct March {
+    // uniform
+    const KParams& P;
+    const KStep& St;
+    Planes in, out;
+    S (*ring)[16][64];
+    Gas<C> g;
+    C r, inv2c, inv2dx, invM[4];
+    int nx, ny, y0, y1, Rb, Re;
+    bool clo, chi;
+    // per lane
+    int lane, lnb, rnb, X;
+    unsigned colx;     // column loaded by this lane
+    bool owner;
+    // row-indexed histories, slot = (row - Rb) % 3
+    C J[3][4], Dl[3], Vo[3];   // partial sums of j_k, dilatation, vorticity
+    C Ss[3], Sth[3];           // S_x[s], S_x[theta]
+    C yprev[4], wpend[4];      // f*_{+y} of the last collided row, pending moments of the row below
+    // reductions of the new state: maxima, and the admissibility witnesses
+    C red_s, red_M[4], min_rho, min_cs2, min_gap, nan_acc;
+
+    __device__ __forceinline__ void reduce(const C* w)
+    {
+        const C irho = fast_rcp(w[0]);
+        const C vx = w[1] * irho, vy = w[2] * irho;
+        const C ee = w[3] * irho - (C)0.5 * (vx * vx + vy * vy);
+        const C PP = eos_pressure<C, EOS>(g, w[0], ee);
+        const C cs2 = eos_cs2<C, EOS>(g, w[0], ee);
+        min_rho = fmin(min_rho, w[0]);
+        min_cs2 = fmin(min_cs2, cs2);
+        if constexpr (EOS == 1) min_gap = fmin(min_gap, (C)1 - g.b * w[0]);
+        nan_acc += (cs2 + PP) * (C)0;   // NaN or Inf anywhere makes this NaN
+        red_s = fmax(red_s, fmax(fabs(vx), fabs(vy)) + fast_sqrt(cs2));
+        const C h = w[3] + PP;
+        red_M[0] = fmax(red_M[0], fmax(fabs(w[1]), fabs(w[2])));
+        red_M[1] = fmax(red_M[1], fmax(fabs(w[1] * vx + PP), fabs(w[2] * vx)));
+        red_M[2] = fmax(red_M[2], fmax(fabs(w[1] * vy), fabs(w[2] * vy + PP)));
+        red_M[3] = fmax(red_M[3], fmax(fabs(h * vx), fabs(h * vy)));
+    }
+
+    // one row of the march; PH = (R - Rb) % 3
+    template <int PH>
+    __device__ __forceinline__ void iter(int R)
+    {
+        constexpr int cR = PH, cR1 = (PH + 2) % 3, cR2 = (PH + 1) % 3, cR3 = PH, cR4 = (PH + 2) % 3;
+        // ---------------- global loads of row R
+        const bool hasA = R <= Re;
+        S fa[16];
+        if (hasA) {
+            const int mrow = (R < 0 || R >= ny) ? wrap_index(R, ny) : R;
+            const unsigned off = ((unsigned)mrow * (unsigned)nx + colx) * (unsigned)sizeof(S);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) fa[j] = bload(in, j, off, S());
+        }
+
+        // ---------------- stage C: row p = R-3 (LDS slot cR3)
+        const int p = R - 3;
+        if (p >= Rb && p >= y0 - 1 && p <= y1 && p <= Re) {
+            const bool plo = clo && p == 0, phi = chi && p == ny - 1;
+            C beta = (C)P.beta_const;
+            if constexpr (SENSOR != 0) {
+                if (plo) { Ss[cR4] = Ss[cR3]; Sth[cR4] = Sth[cR3]; }
+                if (phi) { Ss[cR2] = Ss[cR3]; Sth[cR2] = Sth[cR3]; }
+                const C sbar = (C)0.25 * Ss[cR4] + (C)0.5 * Ss[cR3] + (C)0.25 * Ss[cR2];
+                C thbar = (C)1;
+                if constexpr (SENSOR == 2) thbar = (C)0.25 * Sth[cR4] + (C)0.5 * Sth[cR3] + (C)0.25 * Sth[cR2];
+                const C chiv = fmin(fmax((C)P.c_sensor * sbar * thbar, (C)0), (C)1);
+                beta = (C)P.beta_max - (C)(P.beta_max - P.beta_min) * chiv;
+            }
+            if (St.probe) {
+                if (owner && p >= y0 && p < y1) St.beta_out[(long long)p * nx + X] = (double)beta;
+            } else {
+                // Reprojection to the new link speed (Eq. 40, holding W, J_alpha =
+                // c_old (f_a+ - f_a-) and K = c_old^2 (S_x - S_y)) and relaxation
+                // f* = (1 - 2 beta) f + 2 beta f^eq (Eqs. 20, 22) in moment form:
+                //   f*_{x+-} = W/4 + mu (S_x - S_y) +- (nu D_x + tau Q_x),
+                //   f*_{y+-} = W/4 - mu (S_x - S_y) +- (nu D_y + tau Q_y),
+                // mu = (1 - 2 beta) r^2/4, nu = (1 - 2 beta) r/2, tau = 2 beta/(2 c).
+                C Sx[4], Dx[4], Sy[4], Dy[4], W[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const C a0 = (C)ring[cR3][0 * 4 + k][lane], a1 = (C)ring[cR3][1 * 4 + k][lane];
+                    const C a2 = (C)ring[cR3][2 * 4 + k][lane], a3 = (C)ring[cR3][3 * 4 + k][lane];
+                    Sx[k] = a0 + a1;
+                    Dx[k] = a0 - a1;
+                    Sy[k] = a2 + a3;
+                    Dy[k] = a2 - a3;
+                    W[k] = Sx[k] + Sy[k];
+                }
+                const C irho = fast_rcp(W[0]);
+                const C ux = W[1] * irho, uy = W[2] * irho;
+                const C e = W[3] * irho - (C)0.5 * (ux * ux + uy * uy);
+                const C Pp = eos_pressure<C, EOS>(g, W[0], e);
+                const C h = W[3] + Pp;
+                const C qx[4] = {W[1], W[1] * ux + Pp, W[1] * uy, h * ux};
+                const C qy[4] = {W[2], W[2] * ux, W[2] * uy + Pp, h * uy};
+                const C om = (C)1 - (C)2 * beta;
+                const C mu = om * (C)0.25 * r * r, nu = om * (C)0.5 * r, tau = (C)2 * beta * inv2c;
+                C gx[8], fyp[4], fym[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const C a = (C)0.25 * W[k], m = mu * (Sx[k] - Sy[k]);
+                    const C cx = fma(nu, Dx[k], tau * qx[k]), cy = fma(nu, Dy[k], tau * qy[k]);
+                    const C ap = a + m, am = a - m;
+                    gx[k] = shfl(ap + cx, lnb);       // +x population arriving from x-1
+                    gx[4 + k] = shfl(ap - cx, rnb);   // -x population arriving from x+1
+                    fyp[k] = am + cy;
+                    fym[k] = am - cy;
+                }
+                // streaming stores (pull semantics: a clamped ghost repeats the edge cell)
+                if (owner) {
+                    const unsigned col = (unsigned)X * (unsigned)sizeof(S);
+                    const unsigned rowb = (unsigned)nx * (unsigned)sizeof(S);
+                    if (p >= y0 && p < y1) {
+                        const unsigned b = (unsigned)p * rowb + col;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) bstore(out, j, b, (S)gx[j]);
+                        if (plo)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) bstore(out, 8 + k, b, (S)fyp[k]);
+                        if (phi)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) bstore(out, 12 + k, b, (S)fym[k]);
+                    }
+                    if (p + 1 >= y0 && p + 1 < y1) {
+                        const unsigned b = (unsigned)(p + 1) * rowb + col;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) bstore(out, 8 + k, b, (S)fyp[k]);
+                    }
+                    if (p - 1 >= y0 && p - 1 < y1) {
+                        const unsigned b = (unsigned)(p - 1) * rowb + col;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) bstore(out, 12 + k, b, (S)fym[k]);
+                    }
+                }
+                // reductions of the new state: row p-1 completes with f*_{-y}(p)
+                if (owner && p - 1 >= y0 && p - 1 < y1) {
+                    C w[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) w[k] = wpend[k] + fym[k];
+                    reduce(w);
+                }
+                if (plo)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) yprev[k] = fyp[k];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    wpend[k] = (gx[k] + gx[4 + k]) + yprev[k];
+                    yprev[k] = fyp[k];
+                }
+                if (phi && owner && p >= y0 && p < y1) {
+                    C w[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) w[k] = wpend[k] + fym[k];
+                    reduce(w);
+                }
+            }
+        }
+
+        // ---------------- stage A: row R (LDS slot cR)
+        if (hasA) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) ring[cR][j][lane] = fa[j];
+            if constexpr (SENSOR != 0) {
+                C W[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    W[k] = ((C)fa[0 * 4 + k] + (C)fa[1 * 4 + k]) + ((C)fa[2 * 4 + k] + (C)fa[3 * 4 + k]);
+                const C irho = fast_rcp(W[0]);
+                const C ux = W[1] * irho, uy = W[2] * irho;
+                const C e = W[3] * irho - (C)0.5 * (ux * ux + uy * uy);
+                const C Pp = eos_pressure<C, EOS>(g, W[0], e);
+                const C h = W[3] + Pp;
+                const C qx[4] = {W[1], W[1] * ux + Pp, W[1] * uy, h * ux};
+                const C hq[4] = {(C)0.5 * W[2], (C)0.5 * W[2] * ux, (C)0.5 * (W[2] * uy + Pp), (C)0.5 * h * uy};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    J[cR1][k] += hq[k];                                             // completes row R-1
+                    J[cR][k] += (C)0.5 * (shfl(qx[k], rnb) - shfl(qx[k], lnb));      // x-part of row R
+                    J[cR2][k] = -hq[k];                                             // starts row R+1
+                }
+                C hx = 0, hy = 0;
+                if constexpr (SENSOR == 2) {
+                    hx = ux * inv2dx;
+                    hy = uy * inv2dx;
+                    Dl[cR1] += hy;
+                    Vo[cR1] -= hx;
+                    Dl[cR] += (shfl(ux, rnb) - shfl(ux, lnb)) * inv2dx;
+                    Vo[cR] += (shfl(uy, rnb) - shfl(uy, lnb)) * inv2dx;
+                    Dl[cR2] = -hy;
+                    Vo[cR2] = hx;
+                }
+                if (clo && R == 0) {   // clamped: the row below row 0 is row 0
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) J[cR][k] -= hq[k];
+                    if constexpr (SENSOR == 2) { Dl[cR] -= hy; Vo[cR] += hx; }
+                }
+                if (chi && R == ny - 1) {   // clamped: the row above the top row is itself
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) J[cR][k] += hq[k];
+                    if constexpr (SENSOR == 2) { Dl[cR] += hy; Vo[cR] -= hx; }
+                }
+            }
+        }
+
+        // ---------------- stage B: row q = R-1 (slot cR1)
+        if constexpr (SENSOR != 0) {
+            const int q = R - 1;
+            if (q >= Rb && q <= Re && q >= y0 - 2 && q <= y1 + 1) {
+                C acc = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const C sh = J[cR1][k] * invM[k];
+                    acc = fma(sh, sh, acc);
+                }
+                const C sq = fast_sqrt(acc * (C)0.25);
+                Ss[cR1] = (C)0.25 * shfl(sq, lnb) + (C)0.5 * sq + (C)0.25 * shfl(sq, rnb);
+                if constexpr (SENSOR == 2) {
+                    const C d2 = Dl[cR1] * Dl[cR1];
+                    const C th = d2 * fast_rcp(fma(Vo[cR1], Vo[cR1], d2) + (C)P.eps_theta);
+                    Sth[cR1] = (C)0.25 * shfl(th, lnb) + (C)0.5 * th + (C)0.25 * shfl(th, rnb);
+                }
+            }
+        }
+    }
+};
+
+template <typename S, typename C, int EOS, int SENSOR>
+__global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep St, const S* __restrict__ fin,
+                                                  S* __restrict__ fout)
 {
+    __shared__ S ring[3][16][64];
+
     double c_old, c_new, t, dt;
     bool last;
-    if (!step_clock(P, S, c_old, c_new, t, dt, last)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) write_clock(S, t, dt, c_new, last);
+    if (!step_clock(P, St, c_old, c_new, t, dt, last)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) write_clock(St, t, dt, c_new, last);
 
-    const Gas<T> g = make_gas<T>(P);
-    const bool reproj = (c_old != c_new);
-    const T r = (T)(c_old / c_new);
-    const T inv2c = (T)(0.5 / c_new);
-    T invM[4];
+    March<S, C, EOS, SENSOR> m{P, St};
+    m.in = make_planes(fin, (unsigned)P.plane);
+    m.out = make_planes((const S*)fout, (unsigned)P.plane);
+    m.ring = ring;
+    m.g = make_gas<C>(P);
+    // c_old == c_new gives r = 1: the reprojection is then the identity
+    m.r = (C)(c_old / c_new);
+    m.inv2c = (C)(0.5 / c_new);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double M = S.red_in[1 + k];
-        invM[k] = M > 0.0 ? (T)(1.0 / M) : (T)0;
+        const double M = St.red_in[1 + k];
+        m.invM[k] = M > 0.0 ? (C)(1.0 / M) : (C)0;
     }
-    const T inv2dx = (T)(0.5 / P.dx);
-    const T bmin = (T)P.beta_min, bmax = (T)P.beta_max, csen = (T)P.c_sensor, eps = (T)P.eps_theta;
-    const T bconst = (T)P.beta_const;
-
-    const int nx = P.nx, ny = P.ny;
-    const long long plane = P.plane;
-    const int lane = threadIdx.x;
+    m.inv2dx = (C)(0.5 / P.dx);
+    m.nx = P.nx;
+    m.ny = P.ny;
+    m.lane = threadIdx.x;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int strip = tile % P.nstrips, seg = tile / P.nstrips;
-    const int X = strip * kStripW - 3 + lane;
-    int cx = X;
-    if (X < 0) cx = P.bc[0] == 0 ? wrap_index(X, nx) : 0;
-    else if (X >= nx) cx = P.bc[1] == 0 ? wrap_index(X, nx) : nx - 1;
-    int lnb = lane - 1, rnb = lane + 1;
-    if (P.bc[0] == 1 && X == 0) lnb = lane;
-    if (P.bc[1] == 1 && X == nx - 1) rnb = lane;
-    lnb = max(lnb, 0);
-    rnb = min(rnb, 63);
-    const bool owner = lane >= 3 && lane < 3 + kStripW && X < nx;
-
-    const bool clo = P.bc[2] == 1, chi = P.bc[3] == 1;
-    const int y0 = seg * P.seg_h;
-    const int y1 = min(y0 + P.seg_h, ny);
-    const int Rb = clo ? max(y0 - 3, 0) : y0 - 3;
-    const int Re = chi ? min(y1 + 2, ny - 1) : y1 + 2;
-
-    // row histories (see the file header for the pipeline)
-    T f1[16], f2[16];            // reprojected populations, rows R-1, R-2
-    T qy1[4], qy2[4];            // Q_y, rows R-1, R-2
-    T ux1 = 0, uy1 = 0, ux2 = 0, uy2 = 0;
-    T jx1[4], dil1 = 0, vor1 = 0;  // x-parts of j_k, dilatation, vorticity, row R-1
-    T ss2 = 0, st2 = 0, ss3 = 0, st3 = 0;  // S_x[s], S_x[theta], rows R-2, R-3
-    T xp1[4], xm1[4];            // populations arriving from -x / +x neighbours, row R-3
-    T yp1[4], yp2[4];            // f*_{+y}, rows R-3, R-4
-    T ym1[4];                    // f*_{-y}, row R-3
+    const int halo = (64 - P.strip_w) / 2;
+    m.X = strip * P.strip_w - halo + m.lane;
+    int cx = m.X;
+    if (m.X < 0) cx = P.bc[0] == 0 ? wrap_index(m.X, m.nx) : 0;
+    else if (m.X >= m.nx) cx = P.bc[1] == 0 ? wrap_index(m.X, m.nx) : m.nx - 1;
+    m.colx = (unsigned)cx;
+    m.lnb = m.lane - 1;
+    m.rnb = m.lane + 1;
+    if (P.bc[0] == 1 && m.X == 0) m.lnb = m.lane;
+    if (P.bc[1] == 1 && m.X == m.nx - 1) m.rnb = m.lane;
+    m.lnb = max(m.lnb, 0);
+    m.rnb = min(m.rnb, 63);
+    m.owner = m.lane >= halo && m.lane < halo + P.strip_w && m.X < m.nx;
+    m.clo = P.bc[2] == 1;
+    m.chi = P.bc[3] == 1;
+    m.y0 = seg * P.seg_h;
+    m.y1 = min(m.y0 + P.seg_h, m.ny);
+    m.Rb = m.clo ? max(m.y0 - 3, 0) : m.y0 - 3;
+    m.Re = m.chi ? min(m.y1 + 2, m.ny - 1) : m.y1 + 2;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) f1[j] = f2[j] = (T)0;
+    for (int s = 0; s < 3; ++s) {
+        m.Dl[s] = m.Vo[s] = m.Ss[s] = m.Sth[s] = (C)0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        qy1[k] = qy2[k] = jx1[k] = xp1[k] = xm1[k] = yp1[k] = yp2[k] = ym1[k] = (T)0;
+        for (int k = 0; k < 4; ++k) m.J[s][k] = (C)0;
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m.yprev[k] = m.wpend[k] = m.red_M[k] = (C)0;
+    m.red_s = (C)0;
+    m.min_rho = m.min_cs2 = m.min_gap = (C)1;
+    m.nan_acc = (C)0;
 
-    double red_s = 0.0, red_M[4] = {0.0, 0.0, 0.0, 0.0};
-    int errbits = 0;
-
-    for (int R = Rb; R <= y1 + 2; ++R) {
-        // ---------------- stage A: row R
-        T fa[16], qya[4], jxa[4];
-        T uxa = 0, uya = 0, dila = 0, vora = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) qya[k] = jxa[k] = (T)0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) fa[j] = (T)0;
-        if (R <= Re) {
-            const int mrow = (R < 0 || R >= ny) ? wrap_index(R, ny) : R;
-            const long long base = (long long)mrow * nx + cx;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) fa[j] = fin[j * plane + base];
-            if (reproj) reproject4(fa, r);
-            if constexpr (SENSOR != 0) {
-                T W[4], qxa[4], e;
-                cell_flux<T, EOS>(g, fa, W, uxa, uya, e, qxa, qya);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) jxa[k] = (T)0.5 * (shfl(qxa[k], rnb) - shfl(qxa[k], lnb));
-                if constexpr (SENSOR == 2) {
-                    dila = (shfl(uxa, rnb) - shfl(uxa, lnb)) * inv2dx;   // d u_x / dx
-                    vora = (shfl(uya, rnb) - shfl(uya, lnb)) * inv2dx;   // d u_y / dx
-                }
-            }
-        }
-
-        // ---------------- stage B: row q = R-1
-        const int q = R - 1;
-        T ssq = 0, stq = 0;
-        if constexpr (SENSOR != 0) {
-            if (q >= Rb && q <= Re) {
-                const bool qlo = clo && q == 0, qhi = chi && q == ny - 1;
-                T acc = 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const T qn = qhi ? qy1[k] : qya[k];
-                    const T qp = qlo ? qy1[k] : qy2[k];
-                    const T jk = jx1[k] + (T)0.5 * (qn - qp);
-                    const T sh = jk * invM[k];
-                    acc += sh * sh;
-                }
-                const T sq = sqrt(acc * (T)0.25);
-                ssq = (T)0.25 * shfl(sq, lnb) + (T)0.5 * sq + (T)0.25 * shfl(sq, rnb);
-                if constexpr (SENSOR == 2) {
-                    const T uxn = qhi ? ux1 : uxa, uxp = qlo ? ux1 : ux2;
-                    const T uyn = qhi ? uy1 : uya, uyp = qlo ? uy1 : uy2;
-                    const T dil = dil1 + (uyn - uyp) * inv2dx;
-                    const T vor = vor1 - (uxn - uxp) * inv2dx;
-                    const T d2 = dil * dil;
-                    const T th = d2 / (d2 + vor * vor + eps);
-                    stq = (T)0.25 * shfl(th, lnb) + (T)0.5 * th + (T)0.25 * shfl(th, rnb);
-                }
-            }
-        }
-
-        // ---------------- stage C: row p = R-2
-        const int p = R - 2;
-        T fs[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) fs[j] = (T)0;
-        T xpa[4], xma[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) xpa[k] = xma[k] = (T)0;
-        if (p >= Rb && p <= Re) {
-            T beta = bconst;
-            if constexpr (SENSOR != 0) {
-                const bool plo = clo && p == 0, phi = chi && p == ny - 1;
-                const T sn = phi ? ss2 : ssq, sp = plo ? ss2 : ss3;
-                const T sbar = (T)0.25 * sp + (T)0.5 * ss2 + (T)0.25 * sn;
-                T thbar = (T)1;
-                if constexpr (SENSOR == 2) {
-                    const T tn = phi ? st2 : stq, tp = plo ? st2 : st3;
-                    thbar = (T)0.25 * tp + (T)0.5 * st2 + (T)0.25 * tn;
-                }
-                T chiv = csen * sbar * thbar;
-                chiv = chiv < (T)0 ? (T)0 : (chiv > (T)1 ? (T)1 : chiv);
-                beta = bmax - (bmax - bmin) * chiv;
-            }
-            if (S.probe) {
-                if (owner && p >= y0 && p < y1) S.beta_out[(long long)p * nx + X] = (double)beta;
-            } else {
-                T W[4], qx[4], qy[4], ux, uy, e;
-                cell_flux<T, EOS>(g, f2, W, ux, uy, e, qx, qy);
-                const T tb = (T)2 * beta;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const T w4 = (T)0.25 * W[k];
-                    const T ax = qx[k] * inv2c, ay = qy[k] * inv2c;
-                    fs[0 * 4 + k] = f2[0 * 4 + k] + tb * ((w4 + ax) - f2[0 * 4 + k]);
-                    fs[1 * 4 + k] = f2[1 * 4 + k] + tb * ((w4 - ax) - f2[1 * 4 + k]);
-                    fs[2 * 4 + k] = f2[2 * 4 + k] + tb * ((w4 + ay) - f2[2 * 4 + k]);
-                    fs[3 * 4 + k] = f2[3 * 4 + k] + tb * ((w4 - ay) - f2[3 * 4 + k]);
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    xpa[k] = shfl(fs[0 * 4 + k], lnb);   // +x population arriving from x-1
-                    xma[k] = shfl(fs[1 * 4 + k], rnb);   // -x population arriving from x+1
-                }
-            }
-        }
-
-        // ---------------- stage D: row o = R-3
-        const int o = R - 3;
-        if (!S.probe && o >= y0 && o < y1) {
-            const bool olo = clo && o == 0, ohi = chi && o == ny - 1;
-            T gn[16];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                gn[0 * 4 + k] = xp1[k];
-                gn[1 * 4 + k] = xm1[k];
-                gn[2 * 4 + k] = olo ? yp1[k] : yp2[k];
-                gn[3 * 4 + k] = ohi ? ym1[k] : fs[3 * 4 + k];
-            }
-            if (owner) {
-                const long long base = (long long)o * nx + X;
-#pragma unroll
-                for (int j = 0; j < 16; ++j) fout[j * plane + base] = gn[j];
-                T W[4], qx[4], qy[4], ux, uy, e;
-                cell_flux<T, EOS>(g, gn, W, ux, uy, e, qx, qy);
-                const T cs2 = eos_cs2<T, EOS>(g, W[0], e);
-                errbits |= eos_check<T, EOS>(g, W[0], e, cs2);
-                const T cs = sqrt(cs2 > (T)0 ? cs2 : (T)0);
-                red_s = fmax(red_s, (double)(fmax(fabs(ux), fabs(uy)) + cs));
-#pragma unroll
-                for (int k = 0; k < 4; ++k) red_M[k] = fmax(red_M[k], (double)fmax(fabs(qx[k]), fabs(qy[k])));
-            }
-        }
-
-        // ---------------- shift the row histories
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            f2[j] = f1[j];
-            f1[j] = fa[j];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            qy2[k] = qy1[k];
-            qy1[k] = qya[k];
-            jx1[k] = jxa[k];
-            xp1[k] = xpa[k];
-            xm1[k] = xma[k];
-            yp2[k] = yp1[k];
-            yp1[k] = fs[2 * 4 + k];
-            ym1[k] = fs[3 * 4 + k];
-        }
-        ux2 = ux1; ux1 = uxa;
-        uy2 = uy1; uy1 = uya;
-        dil1 = dila;
-        vor1 = vora;
-        ss3 = ss2; ss2 = ssq;
-        st3 = st2; st2 = stq;
+    const int Rlast = m.y1 + 3;
+    for (int R = m.Rb; R <= Rlast; R += 3) {
+        m.template iter<0>(R);
+        if (R + 1 <= Rlast) m.template iter<1>(R + 1);
+        if (R + 2 <= Rlast) m.template iter<2>(R + 2);
     }
-    if (!S.probe) wave_publish(S, red_s, red_M, 4, errbits);
+    if (!St.probe) {
+        double M[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) M[k] = (double)m.red_M[k];
+        int bits = 0;
+        if (!(m.min_rho > (C)0) || !(m.min_cs2 > (C)0) || !(m.min_gap > (C)0)) bits |= ERR_NONHYP;
+        if (!isfinite(m.nan_acc) || !isfinite(m.red_s)) bits |= ERR_NONFINITE;
+        wave_publish(St, (double)m.red_s, M, 4, bits);
+    }
 }
 
-// ------------------------------------------------------------------ launcher
+// ------------------------------------------------------------------ launchers
 
-template <typename T>
+template <typename S, typename C>
 static hipError_t launch_t(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
 {
     const dim3 grid(p.nstrips * p.nsegs), block(64);
-    const T* in = (const T*)fin;
-    T* out = (T*)fout;
-#define VLBM_CASE(E, SN)                                                                  \
-    if (p.eos == E && p.sensor == SN) {                                                   \
-        hipLaunchKernelGGL((k_step_d2q4<T, E, SN>), grid, block, 0, st, p, s, in, out); \
-        return hipGetLastError();                                                         \
+    const S* in = (const S*)fin;
+    S* out = (S*)fout;
+#define VLBM_CASE(E, SN)                                                                     \
+    if (p.eos == E && p.sensor == SN) {                                                      \
+        hipLaunchKernelGGL((k_step_d2q4<S, C, E, SN>), grid, block, 0, st, p, s, in, out); \
+        return hipGetLastError();                                                            \
     }
     VLBM_CASE(0, 0) VLBM_CASE(0, 1) VLBM_CASE(0, 2) VLBM_CASE(1, 0) VLBM_CASE(1, 1) VLBM_CASE(1, 2)
 #undef VLBM_CASE
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_step_d2q4(const KParams& p, const KStep& s, bool fp32, const void* fin, void* fout,
-                            hipStream_t st)
+hipError_t launch_step_d2q4(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st)
 {
-    return fp32 ? launch_t<float>(p, s, fin, fout, st) : launch_t<double>(p, s, fin, fout, st);
+    switch (prec) {
+    case PREC_FP64: return launch_t<double, double>(p, s, fin, fout, st);
+    case PREC_FP32: return launch_t<float, float>(p, s, fin, fout, st);
+    case PREC_FP32_MIXED: return launch_t<float, double>(p, s, fin, fout, st);
+    }
+    return hipErrorInvalidValue;
 }
 
-}  // namespace vlbm
-
-namespace vlbm {
-
-int step_d2q4_blocks_per_cu(const KParams& p, bool fp32)
+int step_d2q4_blocks_per_cu(const KParams& p, int prec)
 {
     int nb = 0;
-    hipError_t e;
-    if (fp32) {
-        e = p.eos == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, 0, 2>, 64, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, 1, 2>, 64, 0);
-    } else {
-        e = p.eos == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, 0, 2>, 64, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, 1, 2>, 64, 0);
+    hipError_t e = hipErrorInvalidValue;
+    switch (prec) {
+    case PREC_FP64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, double, 0, 2>, 64, 0); break;
+    case PREC_FP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, float, 0, 2>, 64, 0); break;
+    case PREC_FP32_MIXED: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, double, 0, 2>, 64, 0); break;
     }
     return e == hipSuccess ? nb : 0;
 }

@@ -23,7 +23,7 @@ class Solver:
     Keyword arguments follow `vlbm_config` (include/vlbm.h): dim, nx, ny, dx,
     bc (4-tuple), eos, gamma, vdw_a, vdw_b, vdw_R, cfl, retarget_every,
     c_fixed, sensor, beta_const, beta_min, beta_max, c_sensor, eps_theta,
-    precision ("fp64" | "fp32").
+    precision ("fp64" | "fp32" | "fp32_mixed": FP32 populations with FP64 arithmetic).
     """
 
     DEFAULTS = dict(dim=1, nx=100, ny=1, dx=0.01, bc=(1, 1, 1, 1), eos=0, gamma=1.4, vdw_a=0.0, vdw_b=0.0,
@@ -41,7 +41,7 @@ class Solver:
                 for j in range(4):
                     cfg.bc[j] = int(v[j])
             elif k == "precision":
-                cfg.precision = N.FP32 if v in ("fp32", N.FP32) else N.FP64
+                cfg.precision = {"fp64": N.FP64, "fp32": N.FP32, "fp32_mixed": N.FP32_MIXED}.get(v, v)
             else:
                 setattr(cfg, k, v)
         if stream is None:
@@ -53,7 +53,7 @@ class Solver:
         self.NK = self.D + 2
         self.Q = 2 * self.D
         self.shape = (d["ny"], d["nx"])
-        self.fp32 = cfg.precision == N.FP32
+        self.fp32 = cfg.precision in (N.FP32, N.FP32_MIXED)
         h = ctypes.c_void_p()
         st = N.lib().vlbm_create(ctypes.byref(cfg), ctypes.byref(h))
         if st != N.OK:

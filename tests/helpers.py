@@ -42,10 +42,15 @@ def oracle_for(cfg, W0):
 
 
 def rel_errors(a, b):
-    """Per-field relative Linf and relative L1 of a against reference b."""
+    """Relative Linf and relative L1 of a against reference b for each physical
+    field: density, momentum (as a vector: |rho u - rho u_ref| over |rho u_ref|,
+    so a component that happens to be near zero is not divided by itself) and
+    total energy."""
+    D = b.shape[0] - 2
+    fields = [(a[0:1], b[0:1]), (a[1:1 + D], b[1:1 + D]), (a[D + 1:D + 2], b[D + 1:D + 2])]
     out = []
-    for k in range(b.shape[0]):
-        d = np.abs(a[k] - b[k])
-        ref = np.abs(b[k])
+    for x, y in fields:
+        d = np.sqrt(((x - y) ** 2).sum(axis=0))
+        ref = np.sqrt((y ** 2).sum(axis=0))
         out.append((d.max() / max(ref.max(), 1e-300), d.sum() / max(ref.sum(), 1e-300)))
     return out
