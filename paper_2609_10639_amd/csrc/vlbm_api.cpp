@@ -266,12 +266,12 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
               hipMalloc(&ctx->norms_scratch, 16 * sizeof(double)) == hipSuccess &&
               hipHostMalloc((void**)&ctx->host, 48 * sizeof(double)) == hipSuccess &&
               hipHostMalloc((void**)&ctx->host_u, 4 * sizeof(unsigned long long)) == hipSuccess;
-    if (ok) {
-        ctx->adj.nparts = (int)adjoint_partials_count(p);
-        ok = hipMalloc(&ctx->adj.seeds, (size_t)2 * ctx->ncell * sizeof(double)) == hipSuccess &&
-             hipMalloc(&ctx->adj.partials, (size_t)ctx->adj.nparts * 4 * sizeof(double) + 64) == hipSuccess &&
+    if (ok && cfg->retarget_every == 0) {
+        // adjoint scratch only for frozen-speed contexts (the raw entry points)
+        ok = hipMalloc(&ctx->adj.aux, adjoint_aux_elems(p) * sizeof(double)) == hipSuccess &&
+             hipMalloc(&ctx->adj.partials, adjoint_partials_count(p) * 4 * sizeof(double) + 64) == hipSuccess &&
+             hipMalloc(&ctx->adj.qmax, 8 * sizeof(double)) == hipSuccess &&
              hipMalloc(&ctx->adj.argmax, 8 * sizeof(unsigned long long)) == hipSuccess;
-        ctx->adj.err = ctx->raw_err;
     }
     if (!ok) {
         vlbm_destroy(ctx);
@@ -292,7 +292,7 @@ void vlbm_destroy(vlbm_ctx* ctx)
     (void)hipStreamSynchronize(ctx->stream);
     for (void* p : {ctx->f[0], ctx->f[1], (void*)ctx->ring, (void*)ctx->stop_at, (void*)ctx->err,
                     (void*)ctx->raw_err, (void*)ctx->scratchW, (void*)ctx->scratchB, (void*)ctx->partials,
-                    (void*)ctx->norms_scratch, (void*)ctx->adj.seeds, (void*)ctx->adj.partials,
+                    (void*)ctx->norms_scratch, ctx->adj.aux, (void*)ctx->adj.partials, (void*)ctx->adj.qmax,
                     (void*)ctx->adj.argmax})
         if (p) (void)hipFree(p);
     if (ctx->host) (void)hipHostFree(ctx->host);

@@ -28,13 +28,13 @@ hipError_t launch_unpad(int nplanes, long long plane, long long ncell, bool fp32
 
 // adjoint (vlbm_adjoint.hip)
 struct AdjScratch {
-    double* seeds;        // per-cell sensor seeds, 2 planes of ncell (FP64)
-    double* partials;     // per-block partial sums for the normaliser adjoint
-    int nparts;
-    unsigned long long* argmax;  // first arg-max index per component
-    int* err;
+    void* aux;                   // per-cell intermediate fields (adjoint_aux_elems, 8 bytes each)
+    double* partials;            // per-block partial sums of the normaliser adjoint (4 per block)
+    double* qmax;                // grid maxima of |Q_alpha,k| (4)
+    unsigned long long* argmax;  // first maximiser of each |Q_alpha,k| (4)
 };
 size_t adjoint_partials_count(const KParams& p);
+size_t adjoint_aux_elems(const KParams& p);
 hipError_t launch_adjoint_step(const KParams& p, int prec, const void* f_n, const double* norms_n,
                                const void* lam_np1, void* lam_n, const AdjScratch& sc, hipStream_t st);
 hipError_t launch_init_adjoint(const KParams& p, int prec, const double* W0, long long ncell, const void* lam0,
