@@ -75,6 +75,12 @@ typedef struct {
     int32_t eos;             /* VLBM_EOS_IDEAL: P = (gamma-1) rho e (Eq. 15); VLBM_EOS_VDW (Eqs. 16-17) */
     double gamma;            /* heat-capacity ratio; for vdW gamma = 1 + R/c_v */
     double vdw_a, vdw_b, vdw_R;
+    double e_offset;         /* energy gauge of the stored populations: the energy component holds
+                                rho E - e_offset rho.  The update is linear in W and in the flux Q
+                                (Eqs. 20-22), so the shift is exact in real arithmetic; it keeps FP32
+                                populations precise when e >> |u|^2 (dense gases).  Sensor, EOS and
+                                every output (get_W, totals, get_f) use the physical gauge.  0 = off;
+                                the adjoint entry points require 0. */
     double cfl;              /* target Courant number of the retargeting, c = s_max/CFL (Eq. 37) */
     int32_t retarget_every;  /* 1: every step; K > 1: every K steps (forced if s_max > c);
                                 0: link speed frozen at c_fixed (no retarget, no landing) */

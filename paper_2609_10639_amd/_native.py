@@ -29,6 +29,7 @@ class VlbmConfig(ctypes.Structure):
         ("vdw_a", ctypes.c_double),
         ("vdw_b", ctypes.c_double),
         ("vdw_R", ctypes.c_double),
+        ("e_offset", ctypes.c_double),
         ("cfl", ctypes.c_double),
         ("retarget_every", ctypes.c_int32),
         ("c_fixed", ctypes.c_double),

@@ -174,6 +174,7 @@ bool check_config(const vlbm_config* c, std::string& why)
     if (!(c->gamma > 1.0)) return why = "gamma must exceed 1", false;
     if (c->eos == VLBM_EOS_VDW && (!(c->vdw_R > 0) || c->vdw_a < 0 || c->vdw_b < 0))
         return why = "bad van der Waals constants", false;
+    if (!std::isfinite(c->e_offset)) return why = "e_offset must be finite", false;
     if (c->retarget_every < 0) return why = "retarget_every must be >= 0", false;
     if (c->retarget_every > 0 && !(c->cfl > 0 && c->cfl <= 1.0)) return why = "cfl must be in (0, 1]", false;
     if (c->retarget_every == 0 && !(c->c_fixed > 0)) return why = "c_fixed must be positive", false;
@@ -228,6 +229,7 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
     p.vdw_b = cfg->vdw_b;
     p.vdw_R = cfg->eos == VLBM_EOS_VDW ? cfg->vdw_R : 1.0;
     p.inv_cv = (cfg->gamma - 1.0) / p.vdw_R;
+    p.e_off = cfg->e_offset;
     p.cfl = cfg->cfl;
     p.c_fixed = cfg->c_fixed;
     p.retarget_every = cfg->retarget_every;
@@ -370,7 +372,7 @@ vlbm_status vlbm_conserved_totals(vlbm_ctx* ctx, double* out)
     if (!ctx || !out) return fail(ctx, VLBM_EINVAL, "null argument");
     if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
     double* dout = ctx->norms_scratch;
-    HIPCHK(ctx, launch_totals(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, ctx->f[ctx->n & 1], ctx->partials, dout,
+    HIPCHK(ctx, launch_totals(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, ctx->kp.e_off, ctx->f[ctx->n & 1], ctx->partials, dout,
                               ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(ctx->host + 24, dout, ctx->NK * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -384,7 +386,7 @@ vlbm_status vlbm_get_W(vlbm_ctx* ctx, double* out, int32_t out_on_device)
     if (!ctx || !out) return fail(ctx, VLBM_EINVAL, "null argument");
     if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
     double* dst = out_on_device ? out : ctx->scratchW;
-    HIPCHK(ctx, launch_moments(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, ctx->f[ctx->n & 1], dst, ctx->stream));
+    HIPCHK(ctx, launch_moments(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, ctx->kp.e_off, ctx->f[ctx->n & 1], dst, ctx->stream));
     if (!out_on_device)
         HIPCHK(ctx, hipMemcpyAsync(out, dst, (size_t)ctx->NK * ctx->ncell * sizeof(double), hipMemcpyDeviceToHost,
                                    ctx->stream));
@@ -424,11 +426,11 @@ vlbm_status vlbm_get_f(vlbm_ctx* ctx, void* out, int32_t out_on_device)
     if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
     const size_t bytes = (size_t)ctx->nplanes * ctx->ncell * ctx->esize;
     if (out_on_device) {
-        HIPCHK(ctx, launch_unpad(ctx->nplanes, ctx->plane, ctx->ncell, ctx->fp32, ctx->f[ctx->n & 1], out,
+        HIPCHK(ctx, launch_unpad(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, ctx->kp.e_off, ctx->f[ctx->n & 1], out,
                                  ctx->stream));
     } else {
         void* tmp = ctx->f[(ctx->n + 1) & 1];   // the spare buffer is free between steps
-        HIPCHK(ctx, launch_unpad(ctx->nplanes, ctx->plane, ctx->ncell, ctx->fp32, ctx->f[ctx->n & 1], tmp,
+        HIPCHK(ctx, launch_unpad(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, ctx->kp.e_off, ctx->f[ctx->n & 1], tmp,
                                  ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, ctx->stream));
     }
@@ -504,6 +506,13 @@ static vlbm_status need_frozen(vlbm_ctx* ctx)
     return VLBM_OK;
 }
 
+// the adjoint kernels work in the physical energy gauge
+static vlbm_status need_unshifted(vlbm_ctx* ctx)
+{
+    if (ctx->cfg.e_offset != 0.0) return fail(ctx, VLBM_EINVAL, "the adjoint entry points need e_offset == 0");
+    return VLBM_OK;
+}
+
 vlbm_status vlbm_raw_init(vlbm_ctx* ctx, const double* W0, void* f0, double* norms0)
 {
     if (vlbm_status st = need_frozen(ctx)) return st;
@@ -536,6 +545,7 @@ vlbm_status vlbm_raw_adjoint_step(vlbm_ctx* ctx, const void* f_n, const double* 
                                   void* lam_n)
 {
     if (vlbm_status st = need_frozen(ctx)) return st;
+    if (vlbm_status st = need_unshifted(ctx)) return st;
     if (!f_n || !norms_n || !lam_np1 || !lam_n) return fail(ctx, VLBM_EINVAL, "null argument");
     if (lam_np1 == lam_n) return fail(ctx, VLBM_EINVAL, "lam_np1 and lam_n must differ");
     HIPCHK(ctx, launch_adjoint_step(ctx->kp, ctx->prec, f_n, norms_n, lam_np1, lam_n, ctx->adj, ctx->stream));
@@ -545,6 +555,7 @@ vlbm_status vlbm_raw_adjoint_step(vlbm_ctx* ctx, const void* f_n, const double* 
 vlbm_status vlbm_raw_init_adjoint(vlbm_ctx* ctx, const double* W0, const void* lam0, double* W0bar)
 {
     if (vlbm_status st = need_frozen(ctx)) return st;
+    if (vlbm_status st = need_unshifted(ctx)) return st;
     if (!W0 || !lam0 || !W0bar) return fail(ctx, VLBM_EINVAL, "null argument");
     HIPCHK(ctx, launch_init_adjoint(ctx->kp, ctx->prec, W0, ctx->ncell, lam0, W0bar, ctx->stream));
     return VLBM_OK;
@@ -553,13 +564,14 @@ vlbm_status vlbm_raw_init_adjoint(vlbm_ctx* ctx, const double* W0, const void* l
 vlbm_status vlbm_raw_moments(vlbm_ctx* ctx, const void* f, double* W)
 {
     if (!ctx || !f || !W) return fail(ctx, VLBM_EINVAL, "null argument");
-    HIPCHK(ctx, launch_moments(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, f, W, ctx->stream));
+    HIPCHK(ctx, launch_moments(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, ctx->kp.e_off, f, W, ctx->stream));
     return VLBM_OK;
 }
 
 vlbm_status vlbm_raw_moments_adjoint(vlbm_ctx* ctx, const double* Wbar, void* lam)
 {
     if (!ctx || !Wbar || !lam) return fail(ctx, VLBM_EINVAL, "null argument");
+    if (vlbm_status st = need_unshifted(ctx)) return st;
     HIPCHK(ctx, launch_moments_adj(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, Wbar, lam, ctx->stream));
     return VLBM_OK;
 }

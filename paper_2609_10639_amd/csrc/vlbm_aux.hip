@@ -77,7 +77,8 @@ __global__ void k_init_reduce(KParams p, const double* __restrict__ W, long long
 }
 
 // f = f^eq(W0; c0) (Eq. 20); c0 = s_max/CFL from red (or c_fixed).  Block 0
-// writes the clock (t = 0, c0) of slot 0.
+// writes the clock (t = 0, c0) of slot 0.  The energy component is stored in
+// the shifted gauge: W_E - e_off W_rho and Q_E - e_off Q_rho (linear in W, Q).
 template <typename T, int EOS>
 __global__ void k_init_eq(KParams p, const double* __restrict__ W, long long ncell, double* slot0, int frozen,
                           T* __restrict__ f)
@@ -96,12 +97,14 @@ __global__ void k_init_eq(KParams p, const double* __restrict__ W, long long nce
         prim_cell<EOS>(g, D, W + c, ncell, rho, u, e, P, E);
         for (int a = 0; a < D; ++a) {
             const double m = W[(1 + a) * ncell + c];
-            double q[4];
+            double q[4], wv[4];
             q[0] = m;
             for (int b = 0; b < D; ++b) q[1 + b] = m * u[b] + (a == b ? P : 0.0);
-            q[D + 1] = (E + P) * u[a];
+            q[D + 1] = (E + P) * u[a] - p.e_off * m;
+            for (int k = 0; k <= D; ++k) wv[k] = W[k * ncell + c];
+            wv[D + 1] = E - p.e_off * rho;
             for (int k = 0; k < NK; ++k) {
-                const double wk = w * W[k * ncell + c];
+                const double wk = w * wv[k];
                 f[((2 * a) * NK + k) * p.plane + c] = (T)(wk + q[k] * inv2c);
                 f[((2 * a + 1) * NK + k) * p.plane + c] = (T)(wk - q[k] * inv2c);
             }
@@ -109,18 +112,23 @@ __global__ void k_init_eq(KParams p, const double* __restrict__ W, long long nce
     }
 }
 
-// W = sum_i f_i in FP64, (NK, ncell)
+// W = sum_i f_i in FP64, (NK, ncell), back in the physical energy gauge
 template <typename T>
-__global__ void k_moments(int D, long long plane, long long ncell, const T* __restrict__ f, double* __restrict__ W)
+__global__ void k_moments(int D, long long plane, long long ncell, double e_off, const T* __restrict__ f,
+                          double* __restrict__ W)
 {
     const int NK = D + 2, Q = 2 * D;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
-         c += (long long)gridDim.x * blockDim.x)
+         c += (long long)gridDim.x * blockDim.x) {
+        double rho = 0.0;
         for (int k = 0; k < NK; ++k) {
             double acc = 0.0;
             for (int i = 0; i < Q; ++i) acc += (double)f[(i * NK + k) * plane + c];
+            if (k == 0) rho = acc;
+            if (k == NK - 1) acc += e_off * rho;
             W[k * ncell + c] = acc;
         }
+    }
 }
 
 // lam_i = Wbar for every direction i (adjoint of k_moments)
@@ -166,7 +174,8 @@ __global__ void __launch_bounds__(kTotBlock) k_totals_partial(int D, long long p
         for (int k = 0; k < NK; ++k) partials[blockIdx.x * 4 + k] = sh[k][0];
 }
 
-__global__ void __launch_bounds__(kTotBlock) k_totals_final(int NK, int nparts, const double* partials, double* out)
+__global__ void __launch_bounds__(kTotBlock) k_totals_final(int NK, int nparts, double e_off, const double* partials,
+                                                             double* out)
 {
     __shared__ double sh[4][kTotBlock];
     double acc[4] = {0, 0, 0, 0};
@@ -179,17 +188,28 @@ __global__ void __launch_bounds__(kTotBlock) k_totals_final(int NK, int nparts, 
             for (int k = 0; k < NK; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         for (int k = 0; k < NK; ++k) out[k] = sh[k][0];
+        out[NK - 1] += e_off * sh[0][0];
+    }
 }
 
-// populations without plane padding: out[j][cell] = f[j * plane + cell]
+// populations without plane padding, physical energy gauge:
+// out[i][k][cell] = f[(i NK + k) plane + cell] (+ e_off f_i,rho for the energy component)
 template <typename T>
-__global__ void k_unpad(int nplanes, long long plane, long long ncell, const T* __restrict__ f, T* __restrict__ out)
+__global__ void k_unpad(int D, long long plane, long long ncell, double e_off, const T* __restrict__ f,
+                        T* __restrict__ out)
 {
+    const int NK = D + 2, Q = 2 * D;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
          c += (long long)gridDim.x * blockDim.x)
-        for (int j = 0; j < nplanes; ++j) out[j * ncell + c] = f[j * plane + c];
+        for (int i = 0; i < Q; ++i)
+            for (int k = 0; k < NK; ++k) {
+                const int j = i * NK + k;
+                T v = f[j * plane + c];
+                if (k == NK - 1 && e_off != 0.0) v = (T)((double)v + e_off * (double)f[i * NK * plane + c]);
+                out[j * ncell + c] = v;
+            }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -251,13 +271,16 @@ hipError_t launch_init_reduce_only(const KParams& p, const double* W, long long 
     return hipGetLastError();
 }
 
-hipError_t launch_moments(int D, long long plane, long long ncell, bool fp32, const void* f, double* W, hipStream_t st)
+hipError_t launch_moments(int D, long long plane, long long ncell, bool fp32, double e_off, const void* f, double* W,
+                          hipStream_t st)
 {
     const unsigned grid = grid_for(ncell, 256);
     if (fp32)
-        hipLaunchKernelGGL(k_moments<float>, dim3(grid), dim3(256), 0, st, D, plane, ncell, (const float*)f, W);
+        hipLaunchKernelGGL(k_moments<float>, dim3(grid), dim3(256), 0, st, D, plane, ncell, e_off, (const float*)f,
+                           W);
     else
-        hipLaunchKernelGGL(k_moments<double>, dim3(grid), dim3(256), 0, st, D, plane, ncell, (const double*)f, W);
+        hipLaunchKernelGGL(k_moments<double>, dim3(grid), dim3(256), 0, st, D, plane, ncell, e_off,
+                           (const double*)f, W);
     return hipGetLastError();
 }
 
@@ -277,8 +300,8 @@ int totals_nparts(long long ncell)
     return (int)grid_for(ncell, kTotBlock) > 1024 ? 1024 : (int)grid_for(ncell, kTotBlock);
 }
 
-hipError_t launch_totals(int D, long long plane, long long ncell, bool fp32, const void* f, double* partials,
-                         double* out, hipStream_t st)
+hipError_t launch_totals(int D, long long plane, long long ncell, bool fp32, double e_off, const void* f,
+                         double* partials, double* out, hipStream_t st)
 {
     const int nparts = totals_nparts(ncell);
     if (fp32)
@@ -287,19 +310,19 @@ hipError_t launch_totals(int D, long long plane, long long ncell, bool fp32, con
     else
         hipLaunchKernelGGL(k_totals_partial<double>, dim3(nparts), dim3(kTotBlock), 0, st, D, plane, ncell,
                            (const double*)f, partials);
-    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(kTotBlock), 0, st, D + 2, nparts, partials, out);
+    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(kTotBlock), 0, st, D + 2, nparts, e_off, partials, out);
     return hipGetLastError();
 }
 
-hipError_t launch_unpad(int nplanes, long long plane, long long ncell, bool fp32, const void* f, void* out,
+hipError_t launch_unpad(int D, long long plane, long long ncell, bool fp32, double e_off, const void* f, void* out,
                         hipStream_t st)
 {
     const unsigned grid = grid_for(ncell, 256);
     if (fp32)
-        hipLaunchKernelGGL(k_unpad<float>, dim3(grid), dim3(256), 0, st, nplanes, plane, ncell, (const float*)f,
+        hipLaunchKernelGGL(k_unpad<float>, dim3(grid), dim3(256), 0, st, D, plane, ncell, e_off, (const float*)f,
                            (float*)out);
     else
-        hipLaunchKernelGGL(k_unpad<double>, dim3(grid), dim3(256), 0, st, nplanes, plane, ncell, (const double*)f,
+        hipLaunchKernelGGL(k_unpad<double>, dim3(grid), dim3(256), 0, st, D, plane, ncell, e_off, (const double*)f,
                            (double*)out);
     return hipGetLastError();
 }

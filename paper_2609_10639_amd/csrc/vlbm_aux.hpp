@@ -16,14 +16,16 @@ hipError_t launch_init(const KParams& p, bool fp32, const double* W, long long n
                        int frozen, void* f, hipStream_t st);
 hipError_t launch_init_reduce_only(const KParams& p, const double* W, long long ncell, double* red_out, int* err,
                                    hipStream_t st);
-hipError_t launch_moments(int D, long long plane, long long ncell, bool fp32, const void* f, double* W,
+// moments, totals and the population copy return the physical energy gauge
+// (e_off: the gauge shift of the stored populations, KParams::e_off)
+hipError_t launch_moments(int D, long long plane, long long ncell, bool fp32, double e_off, const void* f, double* W,
                           hipStream_t st);
 hipError_t launch_moments_adj(int D, long long plane, long long ncell, bool fp32, const double* Wbar, void* lam,
                               hipStream_t st);
 int totals_nparts(long long ncell);
-hipError_t launch_totals(int D, long long plane, long long ncell, bool fp32, const void* f, double* partials,
-                         double* out, hipStream_t st);
-hipError_t launch_unpad(int nplanes, long long plane, long long ncell, bool fp32, const void* f, void* out,
+hipError_t launch_totals(int D, long long plane, long long ncell, bool fp32, double e_off, const void* f,
+                         double* partials, double* out, hipStream_t st);
+hipError_t launch_unpad(int D, long long plane, long long ncell, bool fp32, double e_off, const void* f, void* out,
                         hipStream_t st);
 
 // adjoint (vlbm_adjoint.hip)

@@ -15,6 +15,7 @@ struct KParams {
     int bc[4];                // x-lo, x-hi, y-lo, y-hi: 0 periodic, 1 outflow (clamped ghost)
     int eos;                  // 0 ideal, 1 van der Waals
     double gamma, vdw_a, vdw_b, vdw_R, inv_cv;
+    double e_off;             // energy gauge: populations carry rho E - e_off rho in the energy component
     double cfl, c_fixed;
     int retarget_every;
     int sensor;               // resolved: 0 off, 1 A (no gate), 2 B (Ducros gate)

@@ -34,6 +34,7 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
     const bool reproj = (c_old != c_new);
     const T r = (T)(c_old / c_new);
     const T inv2c = (T)(0.5 / c_new);
+    const T eoff = (T)P.e_off;   // energy gauge of the stored populations (physical e = e_stored + eoff)
     T invM[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -73,7 +74,7 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
         for (int j = 0; j < 6; ++j) sf[j][s] = f[j];
         const T rho = f[0] + f[3], m = f[1] + f[4], E = f[2] + f[5];
         const T u = m / rho;
-        const T e = E / rho - (T)0.5 * u * u;
+        const T e = E / rho - (T)0.5 * u * u + eoff;
         const T Pp = eos_pressure<T, EOS>(g, rho, e);
         sq[0][s] = m;
         sq[1][s] = m * u + Pp;
@@ -84,10 +85,12 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
     if constexpr (SENSOR != 0) {
         for (int s = threadIdx.x + 1; s < kSlots1 - 1; s += kTile1) {
             const int sl = left_of(s), sr = right_of(s);
-            T acc = 0;
+            T acc = 0, j0 = 0;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const T jk = (T)0.5 * (sq[k][sr] - sq[k][sl]);
+                T jk = (T)0.5 * (sq[k][sr] - sq[k][sl]);
+                if (k == 0) j0 = jk;
+                if (k == 2) jk = fma(eoff, j0, jk);   // physical energy flux: Q_E,stored + eoff Q_rho
                 const T sh = jk * invM[k];
                 acc += sh * sh;
             }
@@ -138,14 +141,14 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
             for (int j = 0; j < 6; ++j) fout[j * plane + X] = (ST)gn[j];
             const T rho = gn[0] + gn[3], m = gn[1] + gn[4], E = gn[2] + gn[5];
             const T u = m / rho;
-            const T e = E / rho - (T)0.5 * u * u;
+            const T e = E / rho - (T)0.5 * u * u + eoff;
             const T Pp = eos_pressure<T, EOS>(g, rho, e);
             const T cs2 = eos_cs2<T, EOS>(g, rho, e);
             errbits |= eos_check<T, EOS>(g, rho, e, cs2);
             red_s = (double)(fabs(u) + sqrt(cs2 > (T)0 ? cs2 : (T)0));
             red_M[0] = (double)fabs(m);
             red_M[1] = (double)fabs(m * u + Pp);
-            red_M[2] = (double)fabs((E + Pp) * u);
+            red_M[2] = (double)fabs((fma(eoff, rho, E) + Pp) * u);
         }
     }
     wave_publish(S, red_s, red_M, 3, errbits);

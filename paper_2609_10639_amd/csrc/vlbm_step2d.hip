@@ -80,28 +80,6 @@ __device__ __forceinline__ void bstore(const Planes& p, int j, unsigned off, flo
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), p.rs[j >> 2], off, (j & 3) * p.plane_bytes, 0);
 }
 
-// W, velocity, internal energy, pressure and the two directional fluxes.
-template <typename C, int EOS>
-__device__ __forceinline__ void cell_flux(const Gas<C>& g, const C* f, C* W, C& ux, C& uy, C* qx, C* qy)
-{
-#pragma unroll
-    for (int k = 0; k < 4; ++k) W[k] = (f[0 * 4 + k] + f[1 * 4 + k]) + (f[2 * 4 + k] + f[3 * 4 + k]);
-    const C irho = fast_rcp(W[0]);
-    ux = W[1] * irho;
-    uy = W[2] * irho;
-    const C e = W[3] * irho - (C)0.5 * (ux * ux + uy * uy);
-    const C P = eos_pressure<C, EOS>(g, W[0], e);
-    const C h = W[3] + P;
-    qx[0] = W[1];
-    qx[1] = W[1] * ux + P;
-    qx[2] = W[1] * uy;
-    qx[3] = h * ux;
-    qy[0] = W[2];
-    qy[1] = W[2] * ux;
-    qy[2] = W[2] * uy + P;
-    qy[3] = h * uy;
-}
-
 template <typename S, typename C, int EOS, int SENSOR>
 struct March {
     // uniform
@@ -111,6 +89,7 @@ struct March {
     S (*ring)[16][64];
     Gas<C> g;
     C r, inv2c, inv2dx, invM[4];
+    C eoff;            // energy gauge of the stored populations (physical e = e_stored + eoff)
     int nx, ny, y0, y1, Rb, Re;
     bool clo, chi;
     // per lane
@@ -128,7 +107,7 @@ struct March {
     {
         const C irho = fast_rcp(w[0]);
         const C vx = w[1] * irho, vy = w[2] * irho;
-        const C ee = w[3] * irho - (C)0.5 * (vx * vx + vy * vy);
+        const C ee = w[3] * irho - (C)0.5 * (vx * vx + vy * vy) + eoff;
         const C PP = eos_pressure<C, EOS>(g, w[0], ee);
         const C cs2 = eos_cs2<C, EOS>(g, w[0], ee);
         min_rho = fmin(min_rho, w[0]);
@@ -136,7 +115,7 @@ struct March {
         if constexpr (EOS == 1) min_gap = fmin(min_gap, (C)1 - g.b * w[0]);
         nan_acc += (cs2 + PP) * (C)0;   // NaN or Inf anywhere makes this NaN
         red_s = fmax(red_s, fmax(fabs(vx), fabs(vy)) + fast_sqrt(cs2));
-        const C h = w[3] + PP;
+        const C h = fma(eoff, w[0], w[3]) + PP;   // physical rho E + P
         red_M[0] = fmax(red_M[0], fmax(fabs(w[1]), fabs(w[2])));
         red_M[1] = fmax(red_M[1], fmax(fabs(w[1] * vx + PP), fabs(w[2] * vx)));
         red_M[2] = fmax(red_M[2], fmax(fabs(w[1] * vy), fabs(w[2] * vy + PP)));
@@ -194,9 +173,9 @@ struct March {
                 }
                 const C irho = fast_rcp(W[0]);
                 const C ux = W[1] * irho, uy = W[2] * irho;
-                const C e = W[3] * irho - (C)0.5 * (ux * ux + uy * uy);
+                const C e = W[3] * irho - (C)0.5 * (ux * ux + uy * uy) + eoff;
                 const C Pp = eos_pressure<C, EOS>(g, W[0], e);
-                const C h = W[3] + Pp;
+                const C h = W[3] + Pp;   // stored gauge: the energy flux is Q_E - eoff Q_rho
                 const C qx[4] = {W[1], W[1] * ux + Pp, W[1] * uy, h * ux};
                 const C qy[4] = {W[2], W[2] * ux, W[2] * uy + Pp, h * uy};
                 const C om = (C)1 - (C)2 * beta;
@@ -273,7 +252,7 @@ struct March {
                     W[k] = ((C)fa[0 * 4 + k] + (C)fa[1 * 4 + k]) + ((C)fa[2 * 4 + k] + (C)fa[3 * 4 + k]);
                 const C irho = fast_rcp(W[0]);
                 const C ux = W[1] * irho, uy = W[2] * irho;
-                const C e = W[3] * irho - (C)0.5 * (ux * ux + uy * uy);
+                const C e = W[3] * irho - (C)0.5 * (ux * ux + uy * uy) + eoff;
                 const C Pp = eos_pressure<C, EOS>(g, W[0], e);
                 const C h = W[3] + Pp;
                 const C qx[4] = {W[1], W[1] * ux + Pp, W[1] * uy, h * ux};
@@ -315,7 +294,9 @@ struct March {
                 C acc = 0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const C sh = J[cR1][k] * invM[k];
+                    // energy activity of the physical flux: j_E = j_E,stored + eoff j_rho
+                    const C jk = k == 3 ? fma(eoff, J[cR1][0], J[cR1][3]) : J[cR1][k];
+                    const C sh = jk * invM[k];
                     acc = fma(sh, sh, acc);
                 }
                 const C sq = fast_sqrt(acc * (C)0.25);
@@ -355,6 +336,7 @@ __global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep S
         m.invM[k] = M > 0.0 ? (C)(1.0 / M) : (C)0;
     }
     m.inv2dx = (C)(0.5 / P.dx);
+    m.eoff = (C)P.e_off;
     m.nx = P.nx;
     m.ny = P.ny;
     m.lane = threadIdx.x;

@@ -21,13 +21,13 @@ class Solver:
     """VLBM solver on the current GPU.
 
     Keyword arguments follow `vlbm_config` (include/vlbm.h): dim, nx, ny, dx,
-    bc (4-tuple), eos, gamma, vdw_a, vdw_b, vdw_R, cfl, retarget_every,
+    bc (4-tuple), eos, gamma, vdw_a, vdw_b, vdw_R, e_offset, cfl, retarget_every,
     c_fixed, sensor, beta_const, beta_min, beta_max, c_sensor, eps_theta,
     precision ("fp64" | "fp32" | "fp32_mixed": FP32 populations with FP64 arithmetic).
     """
 
     DEFAULTS = dict(dim=1, nx=100, ny=1, dx=0.01, bc=(1, 1, 1, 1), eos=0, gamma=1.4, vdw_a=0.0, vdw_b=0.0,
-                    vdw_R=1.0, cfl=0.5, retarget_every=1, c_fixed=0.0, sensor=3, beta_const=1.0, beta_min=0.75,
+                    vdw_R=1.0, e_offset=0.0, cfl=0.5, retarget_every=1, c_fixed=0.0, sensor=3, beta_const=1.0, beta_min=0.75,
                     beta_max=1.0, c_sensor=4.0, eps_theta=1e-12, precision="fp64")
 
     def __init__(self, stream=None, **kw):

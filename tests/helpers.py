@@ -34,8 +34,17 @@ def bzt2d_case(n=256):
     return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D, **VDW), 0.2
 
 
+def energy_gauge(W0):
+    """Mean specific internal energy of W0: the e_offset that centres the stored
+    energy component of FP32 populations."""
+    D = W0.shape[0] - 2
+    rho = W0[0]
+    ke = 0.5 * sum(W0[1 + a] ** 2 for a in range(D)) / rho
+    return float(np.mean((W0[D + 1] - ke) / rho))
+
+
 def oracle_for(cfg, W0):
-    kw = {k: v for k, v in cfg.items() if k != "precision"}
+    kw = {k: v for k, v in cfg.items() if k not in ("precision", "e_offset")}
     o = core.Oracle(**kw)
     o.init(W0)
     return o
