@@ -1,18 +1,33 @@
 """Benchmark of the VLBM hot path on one MI355X.
 
-Workload: the 2-D isentropic vortex (periodic [0,10]^2, strength 5, background
-flow (1,1), ideal gas gamma = 1.4, Sensor B, CFL 0.45) at its largest grid,
-1024^2.  A step is one fused D2Q4 lattice update of the whole grid (moments,
-EOS closure, retarget + reprojection, sensor, collision, streaming and the
-reductions for the next step), launched through the C ABI.
+Headline workload: the 2-D isentropic vortex (periodic [0,10]^2, strength 5,
+background flow (1,1), ideal gas gamma = 1.4, Sensor B, CFL 0.45) on its
+largest grid, 1024^2, FP64.  A step is one fused D2Q4 lattice update of the
+whole grid (moments, EOS closure, retarget + reprojection, sensor, collision,
+streaming and the reductions for the next step), launched through the C ABI;
+`value` is lattice updates per second (MLUPS) of that step.
 
-Printed: one JSON line with MLUPS of the FP64 step (`value`), the FP32 form
-beside it, the HBM roofline of the dominant kernel (algorithmic bytes
-2 * 16 * sizeof(double) per lattice update, timed with HIP events on the
-stream the kernel runs on), a larger 4096^2 grid for a working set well above
-the 256 MB last-level cache, and the FP64 CPU oracle timed on a bounded sample.
+Beside it on the same JSON line:
+  roofline      the fused step kernel against the 8 TB/s HBM peak, from the
+                algorithmic bytes 2 * 16 * sizeof(double) per lattice update
+                and the step time measured with HIP events on the stream the
+                kernel runs on; `traffic` = measured HBM bytes per launch
+                from the committed hardware-counter summary when it was
+                taken on the current kernel source (else null);
+  fp32          the FP32 forms (FP32 arithmetic; FP32 storage with FP64
+                arithmetic) on the same grid;
+  grid_4096     FP64 and FP32 at 4096^2, a working set far above the 256 MB
+                last-level cache (the grid for roofline claims);
+  riemann4096   four-quadrant Riemann configuration 3, 4096^2, FP32, outflow;
+  d1q2          the D1Q2 step (Sod shock tube data) at 2^26 cells;
+  adjoint       adjoint/forward step-cost ratio on the adjoint workload
+                (1024^2 perturbed vortex, frozen dt = 1/625, Sensor B), per
+                step and end to end (checkpointed forward + backward);
+  cpu_baseline  the FP64 CPU oracle (OpenMP) on a bounded sample of the
+                headline workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +37,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "d2q4_fp64_vortex1024_traffic.txt")
+KERNEL_SOURCES = ("paper_2609_10639_amd/csrc/vlbm_step2d.hip", "paper_2609_10639_amd/csrc/vlbm_common.hpp")
 
 
 def parse():
@@ -33,56 +50,170 @@ def parse():
     ap.add_argument("--big-grid", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline measurement only")
-    ap.add_argument("--cpu-steps", type=int, default=100)
-    ap.add_argument("--only", default="", help="profiling aid: fp64 | fp32 | big64 | big32 | copy "
-                                                "(headline otherwise)")
+    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--only", default="", help="profiling aid: fp64 | fp32 | fp32_mixed | big64 | big32 | "
+                                                "riemann32 | d1q2_64 | d1q2_32 | adjoint32 | adjoint64 | copy")
     return ap.parse_args()
 
+
+# ------------------------------------------------------------------ workloads
 
 def vortex_cfg(n):
     from paper_2609_10639_amd import problems as pr
     W0, dx = pr.vortex(n)
-    cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D,
-               **pr.IDEAL_AIR.config())
-    return W0, cfg
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D,
+                    **pr.IDEAL_AIR.config())
 
 
-def time_steps(n, precision, steps, warmup):
-    """Run `warmup` untimed steps then time `steps` steps with HIP events on the
-    library's stream.  Returns (ms per step, cells)."""
+def riemann_cfg(n):
+    from paper_2609_10639_amd import problems as pr
+    W0, dx = pr.riemann2d(n, 3)
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2, **pr.SENSOR_2D,
+                    **pr.IDEAL_AIR.config())
+
+
+def sod_cfg(n):
+    from paper_2609_10639_amd import problems as pr
+    W0, dx = pr.sod(n)
+    return W0, dict(dim=1, nx=n, ny=1, dx=dx, bc=(1, 1, 1, 1), cfl=0.5, sensor=1, **pr.SENSOR_1D,
+                    **pr.IDEAL_AIR.config())
+
+
+def adjoint_cfg(n=1024, steps=625):
+    from paper_2609_10639_amd import problems as pr
+    W0, dx = pr.vortex_perturbed(n, amplitude=1e-3, seed=42)
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), retarget_every=0, c_fixed=dx * steps, sensor=2,
+                    **pr.SENSOR_2D, **pr.IDEAL_AIR.config())
+
+
+# ------------------------------------------------------------------ timing
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_steps(W0, cfg, precision, steps, warmup):
+    """`warmup` untimed steps, then `steps` steps timed with HIP events on the
+    library's stream, synchronised on both sides.  Returns ms per step."""
     import torch
     from paper_2609_10639_amd import Solver
-    W0, cfg = vortex_cfg(n)
     s = Solver(precision=precision, **cfg)
     s.init(W0)
     if warmup:
         s.step(warmup)
-    stream = s.stream
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
+    e0, e1 = _events()
+    e0.record(s.stream)
     done = s.step(steps)
-    e1.record(stream)
+    e1.record(s.stream)
     torch.cuda.synchronize()
-    assert done == steps
-    ms = e0.elapsed_time(e1) / steps
+    assert done == steps, (done, steps)
     s.close()
-    return ms, n * n
+    return e0.elapsed_time(e1) / steps
 
 
-def bytes_per_lu(precision):
-    return 2 * 16 * (8 if precision == "fp64" else 4)
+def bytes_per_lu(dim, precision):
+    nf = 16 if dim == 2 else 6
+    return 2 * nf * (8 if precision == "fp64" else 4)
 
 
-def roofline(ms, cells, precision):
-    gbs = bytes_per_lu(precision) * cells / (ms * 1e-3) / 1e9
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(cells):
+    """HBM bytes per launch of the FP64 step at `cells`, from the committed
+    counter summary, if it was taken on the current kernel source."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv.get("cells", -1)) != cells:
+            return None
+        return int(float(kv["hbm_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def roofline(ms, cells, dim, precision, traffic=None):
+    gbs = bytes_per_lu(dim, precision) * cells / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+
+def line(ms, cells, dim, precision):
+    return {"MLUPS": round(cells / ms / 1e3, 1), "ms_per_step": round(ms, 5),
+            "roofline": roofline(ms, cells, dim, precision)}
+
+
+def adjoint_ratio(precision, n=1024, nsteps=625, reps=50):
+    """Per-step cost of the adjoint step against the forward step on the same
+    state (raw entry points, frozen link speed), and the end-to-end cost of
+    the checkpointed backward pass against the forward pass."""
+    import torch
+    from paper_2609_10639_amd import Solver
+    from paper_2609_10639_amd.adjoint import Rollout
+    W0, cfg = adjoint_cfg(n, nsteps)
+    s = Solver(precision=precision, **cfg)
+    W = torch.tensor(W0, device="cuda")
+    fa, fb = s.new_populations(), s.new_populations()
+    na, nb = s.new_norms(), s.new_norms()
+    s.raw_init(W, fa, na)
+    for _ in range(5):
+        s.raw_step(fa, na, fb, nb)
+        s.raw_adjoint_step(fa, na, fb, fa.clone())
+    lam0, lam1 = s.new_populations(), s.new_populations()
+    lam0.fill_(1e-3)
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record(s.stream)
+    for i in range(reps):
+        if i % 2 == 0:
+            s.raw_step(fa, na, fb, nb)
+        else:
+            s.raw_step(fb, nb, fa, na)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1) / reps
+    e0, e1 = _events()
+    e0.record(s.stream)
+    for i in range(reps):
+        if i % 2 == 0:
+            s.raw_adjoint_step(fa, na, lam0, lam1)
+        else:
+            s.raw_adjoint_step(fa, na, lam1, lam0)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    t_adj = e0.elapsed_time(e1) / reps
+    # end to end: checkpointed forward, then backward (replay + adjoint)
+    run = Rollout(s, nsteps)
+    rho_t = torch.tensor(W0[0], device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    WN, ck = run.forward(W)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    WNbar = torch.zeros_like(WN)
+    WNbar[0] = (WN[0] - rho_t) * cfg["dx"] ** 2
+    run.backward(W, ck, WNbar)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.close()
+    return {"precision": precision, "grid": [n, n], "fwd_ms_per_step": round(t_fwd, 5),
+            "adj_ms_per_step": round(t_adj, 5), "step_ratio": round(t_adj / t_fwd, 3),
+            "end_to_end": {"steps": nsteps, "checkpoint_every": run.K, "forward_s": round(t1 - t0, 4),
+                           "backward_s": round(t2 - t1, 4), "ratio": round((t2 - t1) / (t1 - t0), 3)}}
 
 
 def cpu_baseline(n, steps):
-    import numpy as np
     from oracle import core
     W0, cfg = vortex_cfg(n)
     o = core.Oracle(**cfg)
@@ -92,47 +223,63 @@ def cpu_baseline(n, steps):
     for _ in range(steps):
         o.step()
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(n * n * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": "%d FP64 steps of the %dx%d vortex (%.1f s)" % (steps, n, n, dt)}
+    return {"value": round(n * n * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": core.threads(),
+            "kind": "oracle", "sample": "%d FP64 steps of the %dx%d vortex (%.1f s, OpenMP)" % (steps, n, n, dt)}
+
+
+def copy_bw(nbytes, steps, warmup):
+    """Plain device copy of `nbytes`: attainable bandwidth and the reference for
+    the hardware byte counters."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(warmup):
+        dst.copy_(src)
+    e0, e1 = _events()
+    e0.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": round(ms, 5),
+            "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
+# ------------------------------------------------------------------ main
+
+def only(a):
+    o = a.only
+    if o == "copy":
+        return dict(only=o, **copy_bw(16 * a.big_grid * a.big_grid * 8, a.steps, a.warmup))
+    if o.startswith("adjoint"):
+        return dict(only=o, **adjoint_ratio("fp32" if o.endswith("32") else "fp64"))
+    prec = {"fp64": "fp64", "fp32": "fp32", "fp32_mixed": "fp32_mixed", "big64": "fp64", "big32": "fp32",
+            "riemann32": "fp32", "d1q2_64": "fp64", "d1q2_32": "fp32"}[o]
+    if o.startswith("d1q2"):
+        W0, cfg = sod_cfg(1 << 26)
+    elif o == "riemann32":
+        W0, cfg = riemann_cfg(a.big_grid)
+    else:
+        W0, cfg = vortex_cfg(a.big_grid if o.startswith("big") else a.grid)
+    ms = time_steps(W0, cfg, prec, a.steps, a.warmup)
+    return dict(only=o, grid=[cfg["ny"], cfg["nx"]], **line(ms, cfg["nx"] * cfg["ny"], cfg["dim"], prec))
 
 
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
-              file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if a.only == "copy":
-        # plain HBM copy of the FP64 D2Q4 population array at the big grid:
-        # the reference for the hardware byte counters and attainable bandwidth
-        nbytes = 16 * a.big_grid * a.big_grid * 8
-        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(a.warmup):
-            dst.copy_(src)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(a.steps):
-            dst.copy_(src)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / a.steps
-        print(json.dumps({"only": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "ms": ms,
-                          "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}))
-        return
     if a.only:
-        n = a.big_grid if a.only.startswith("big") else a.grid
-        prec = "fp32" if a.only.endswith("32") else "fp64"
-        ms, cells = time_steps(n, prec, a.steps, a.warmup)
-        print(json.dumps({"only": a.only, "grid": n, "ms_per_step": ms, "MLUPS": cells / ms / 1e3,
-                          "roofline": roofline(ms, cells, prec)}))
+        print(json.dumps(only(a)), flush=True)
         return
 
-    ms64, cells = time_steps(a.grid, "fp64", a.steps, a.warmup)
+    W0, cfg = vortex_cfg(a.grid)
+    cells = a.grid * a.grid
+    ms64 = time_steps(W0, cfg, "fp64", a.steps, a.warmup)
     out = {
         "metric": "MLUPS and % of HBM roofline (FP64 vs FP32), adjoint/forward step-cost ratio",
         "value": round(cells / ms64 / 1e3, 1),
@@ -146,24 +293,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "isentropic vortex, periodic [0,10]^2, strength 5, background (1,1), "
-                               "D2Q4, ideal gas 1.4, Sensor B, CFL 0.45", "grid": [a.grid, a.grid],
-                   "cells": cells},
-        "roofline": roofline(ms64, cells, "fp64"),
+        "config": {"workload": "isentropic vortex advection, periodic [0,10]^2, strength 5, background (1,1), "
+                               "ideal gas 1.4, D2Q4, Sensor B, CFL 0.45", "grid": [a.grid, a.grid], "cells": cells},
+        "roofline": roofline(ms64, cells, 2, "fp64", measured_traffic(cells)),
     }
     if not a.no_extra:
-        ms32, _ = time_steps(a.grid, "fp32", a.steps, a.warmup)
-        out["fp32"] = {"MLUPS": round(cells / ms32 / 1e3, 1), "ms_per_step": round(ms32, 5),
-                       "roofline": roofline(ms32, cells, "fp32")}
-        big = {}
-        for prec in ("fp64", "fp32"):
-            msb, cb = time_steps(a.big_grid, prec, max(20, a.steps // 4), 5)
-            big[prec] = {"MLUPS": round(cb / msb / 1e3, 1), "ms_per_step": round(msb, 4),
-                         "roofline": roofline(msb, cb, prec)}
-        out["grid_%d" % a.big_grid] = big
+        out["fp32"] = {p: line(time_steps(W0, cfg, p, a.steps, a.warmup), cells, 2, p)
+                       for p in ("fp32", "fp32_mixed")}
+        nb = a.big_grid
+        Wb, cb = vortex_cfg(nb)
+        ksteps = max(20, a.steps // 4)
+        out["grid_%d" % nb] = {p: line(time_steps(Wb, cb, p, ksteps, 5), nb * nb, 2, p)
+                               for p in ("fp64", "fp32", "fp32_mixed")}
+        del Wb
+        Wr, cr = riemann_cfg(nb)
+        out["riemann%d" % nb] = {p: line(time_steps(Wr, cr, p, ksteps, 5), nb * nb, 2, p) for p in ("fp32", "fp64")}
+        del Wr
+        W1, c1 = sod_cfg(1 << 26)
+        out["d1q2"] = {"cells": 1 << 26, **{p: line(time_steps(W1, c1, p, ksteps, 5), 1 << 26, 1, p)
+                                            for p in ("fp64", "fp32")}}
+        del W1
+        out["adjoint"] = [adjoint_ratio("fp32"), adjoint_ratio("fp64")]
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.grid, a.cpu_steps)
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

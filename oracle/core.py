@@ -68,6 +68,7 @@ def lib():
         dp = P(ctypes.c_double)
         L.orc_create.argtypes = [P(OrcConfig), P(ctypes.c_void_p)]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_threads.restype = ctypes.c_int
         L.orc_init.argtypes = [ctypes.c_void_p, dp]
         L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_run_to_time.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_long, P(ctypes.c_long)]
@@ -184,6 +185,11 @@ class Oracle:
         out = np.empty(self.NK)
         lib().orc_totals(self._h, _dp(out))
         return out
+
+
+def threads():
+    """OpenMP threads the oracle's loops run on."""
+    return int(lib().orc_threads())
 
 
 def eos(cfg, rho, e):

@@ -39,6 +39,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <float.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_LANDED 1
@@ -630,4 +633,14 @@ void orc_equilibrium(const orc_config* g, double c, const double* W, double* feq
             for (int a = 0; a < D; ++a) cdotQ += c * evec(i, a) * flux[a][k];
             feq[i * NK + k] = W[k] / (2.0 * D) + cdotQ / (2.0 * c * c);
         }
+}
+
+/* threads the OpenMP loops of this library use (1 without OpenMP) */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
