@@ -161,7 +161,7 @@ __device__ __forceinline__ void load_cell(const S* f, long long plane, int Q, in
 // ---------------------------------------------------------------- P1
 template <typename S, typename C, int EOS, int D>
 __global__ void __launch_bounds__(kAdjBlock) k_adj_p1(KParams p, const S* __restrict__ f, C* __restrict__ aux,
-                                                       double* __restrict__ qmax)
+                                                       double* __restrict__ qpart)
 {
     using L = AuxLayout<D>;
     constexpr int NK = D + 2, Q = 2 * D;
@@ -184,10 +184,36 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_p1(KParams p, const S* __rest
             aux[(L::A1 + D * NK + a) * ncell + c] = u[a];
         }
     }
+    // block maximum into qpart[blockIdx] (no same-address atomics); k_adj_qmax folds the blocks
+    __shared__ double sh[kAdjBlock / 64][4];
     for (int k = 0; k < NK; ++k) {
         const double v = wave_max(mx[k]);
-        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&qmax[k], v);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][k] = v;
     }
+    __syncthreads();
+    if (threadIdx.x < NK) {
+        double v = sh[0][threadIdx.x];
+        for (int w = 1; w < kAdjBlock / 64; ++w) v = fmax(v, sh[w][threadIdx.x]);
+        qpart[blockIdx.x * 4 + threadIdx.x] = v;
+    }
+}
+
+// qmax[k] = max over the blocks of P1 (one workgroup)
+__global__ void __launch_bounds__(kAdjBlock) k_adj_qmax(int NK, int nparts, const double* __restrict__ qpart,
+                                                         double* __restrict__ qmax)
+{
+    __shared__ double sh[4][kAdjBlock];
+    double acc[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nparts; b += kAdjBlock)
+        for (int k = 0; k < NK; ++k) acc[k] = fmax(acc[k], qpart[b * 4 + k]);
+    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = kAdjBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + s]);
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < NK) qmax[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // ---------------------------------------------------------------- P2
@@ -490,16 +516,30 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_p5(KParams p, const S* __rest
 
 // ---------------------------------------------------------------- P6
 template <typename S, typename C, int EOS, int D>
-__global__ void k_adj_p6(KParams p, const S* __restrict__ f, const double* __restrict__ partials, int nparts,
+__global__ void __launch_bounds__(kAdjBlock) k_adj_p6(KParams p, const S* __restrict__ f, const double* __restrict__ partials, int nparts,
                          const unsigned long long* __restrict__ argmax, S* __restrict__ lam_out)
 {
     constexpr int NK = D + 2, Q = 2 * D;
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // M-bar_k = sum of the P4 block partials: fixed assignment to threads and a
+    // fixed tree, so the sum is deterministic
+    __shared__ double sh[4][kAdjBlock];
+    {
+        double acc[4] = {0, 0, 0, 0};
+        for (int b = threadIdx.x; b < nparts; b += kAdjBlock)
+            for (int k = 0; k < NK; ++k) acc[k] += partials[b * 4 + k];
+        for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int s = kAdjBlock / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s)
+                for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x != 0) return;
     const long long ncell = (long long)p.nx * p.ny;
     const Gas<C> g = make_gas<C>(p);
     for (int k = 0; k < NK; ++k) {
-        double Mb = 0.0;
-        for (int b = 0; b < nparts; ++b) Mb += partials[b * 4 + k];
+        const double Mb = sh[k][0];
         if (Mb == 0.0 || argmax[k] == ~0ull) continue;
         const int a = (int)(argmax[k] / (unsigned long long)ncell);
         const long long c = (long long)(argmax[k] % (unsigned long long)ncell);
@@ -579,7 +619,9 @@ static hipError_t adj_t(const KParams& p, const void* f_n, const double* norms, 
     S* lo = (S*)lam_n;
     C* aux = (C*)sc.aux;
     hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(64), 0, st, sc.qmax, sc.argmax);
-    hipLaunchKernelGGL((k_adj_p1<S, C, EOS, D>), dim3(nb), dim3(kAdjBlock), 0, st, p, f, aux, sc.qmax);
+    // P1 block maxima go through the partials buffer, which P4 reuses afterwards
+    hipLaunchKernelGGL((k_adj_p1<S, C, EOS, D>), dim3(nb), dim3(kAdjBlock), 0, st, p, f, aux, sc.partials);
+    hipLaunchKernelGGL(k_adj_qmax, dim3(1), dim3(kAdjBlock), 0, st, D + 2, nb, (const double*)sc.partials, sc.qmax);
     hipLaunchKernelGGL((k_adj_p2<C, D, SENSOR>), dim3(nb), dim3(kAdjBlock), 0, st, p, norms, aux,
                        (const double*)sc.qmax, sc.argmax);
     hipLaunchKernelGGL((k_adj_p3<S, C, EOS, D, SENSOR>), dim3(nb), dim3(kAdjBlock), 0, st, p, f, lam, aux);
@@ -587,7 +629,7 @@ static hipError_t adj_t(const KParams& p, const void* f_n, const double* norms, 
     hipLaunchKernelGGL((k_adj_p5<S, C, EOS, D, SENSOR>), dim3(nb), dim3(kAdjBlock), 0, st, p, f, lam,
                        (const C*)aux, lo);
     if (SENSOR != 0)
-        hipLaunchKernelGGL((k_adj_p6<S, C, EOS, D>), dim3(1), dim3(64), 0, st, p, f, (const double*)sc.partials, nb,
+        hipLaunchKernelGGL((k_adj_p6<S, C, EOS, D>), dim3(1), dim3(kAdjBlock), 0, st, p, f, (const double*)sc.partials, nb,
                            (const unsigned long long*)sc.argmax, lo);
     return hipGetLastError();
 }

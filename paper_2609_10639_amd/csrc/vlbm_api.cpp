@@ -4,8 +4,9 @@
 //
 // Device state
 //   f[2]       two population buffers; state n lives in f[n & 1]
-//   ring       3 slots x 8 doubles: [t, c, s_max, M_0..M_{D+1}, -]; state n
-//              has its clock and reductions in slot n % 3
+//   ring       3 slots of kSlot doubles: [t, c] and kRedCopies copies of the
+//              reductions [s_max, M_0..M_{D+1}]; state n has its clock and
+//              reductions in slot n % 3
 //   stop_at    launches with index >= stop_at return immediately (landing or
 //              an inadmissible state), so a batch never overruns
 //   err        admissibility bits of the state stop_at
@@ -24,6 +25,9 @@
 
 using namespace vlbm;
 
+// pinned host mirror: the three ring slots, then scratch for totals and checkpoints
+constexpr int kHostAux = 3 * kSlot;
+
 struct vlbm_ctx {
     vlbm_config cfg;
     KParams kp;
@@ -40,7 +44,7 @@ struct vlbm_ctx {
     double* scratchB = nullptr;    // (ncell) FP64
     double* partials = nullptr;    // totals partials
     double* norms_scratch = nullptr;
-    double* host = nullptr;        // pinned readback: ring (24) + totals (4)
+    double* host = nullptr;        // pinned readback: ring (3 kSlot), then kHostAux scratch doubles
     unsigned long long* host_u = nullptr;
     int* raw_err = nullptr;
     AdjScratch adj{};
@@ -102,7 +106,8 @@ int choose_seg_h(const KParams& p, int prec)
 
 vlbm_status sync_readback(vlbm_ctx* ctx)
 {
-    HIPCHK(ctx, hipMemcpyAsync(ctx->host, ctx->ring, 24 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host, ctx->ring, 3 * kSlot * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(ctx->host_u, ctx->stop_at, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync((char*)(ctx->host_u + 1), ctx->err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -113,14 +118,16 @@ vlbm_status sync_readback(vlbm_ctx* ctx)
 hipError_t launch_one(vlbm_ctx* ctx, long long n, double t_end)
 {
     KStep s{};
-    double* slot = ctx->ring + 8 * (n % 3);
-    double* next = ctx->ring + 8 * ((n + 1) % 3);
-    double* after = ctx->ring + 8 * ((n + 2) % 3);
+    double* slot = ctx->ring + kSlot * (n % 3);
+    double* next = ctx->ring + kSlot * ((n + 1) % 3);
+    double* after = ctx->ring + kSlot * ((n + 2) % 3);
     s.clock_in = slot;
     s.clock_out = next;
-    s.red_in = slot + 2;
-    s.red_out = next + 2;
-    s.red_clear = after + 2;
+    s.red_in = slot + kRedBase;
+    s.red_out = next + kRedBase;
+    s.red_clear = after + kRedBase;
+    s.red_copies = kRedCopies;
+    s.red_stride = kRedStride;
     s.stop_at = ctx->stop_at;
     s.err = ctx->err;
     s.n = n;
@@ -144,7 +151,7 @@ vlbm_status run_batch(vlbm_ctx* ctx, long long count, double t_end, long long* e
     long long nn = n0 + count;
     if (stop != ~0ull && (long long)stop < nn) nn = (long long)stop;
     ctx->n = nn;
-    const double* slot = ctx->host + 8 * (nn % 3);
+    const double* slot = ctx->host + kSlot * (nn % 3);
     ctx->t = slot[0];
     ctx->c = slot[1];
     *executed = nn - n0;
@@ -258,7 +265,7 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
 
     const size_t fbytes = (size_t)ctx->nplanes * ctx->plane * ctx->esize;
     bool ok = hipMalloc(&ctx->f[0], fbytes) == hipSuccess && hipMalloc(&ctx->f[1], fbytes) == hipSuccess &&
-              hipMalloc(&ctx->ring, 24 * sizeof(double)) == hipSuccess &&
+              hipMalloc(&ctx->ring, 3 * kSlot * sizeof(double)) == hipSuccess &&
               hipMalloc(&ctx->stop_at, sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc(&ctx->err, sizeof(int)) == hipSuccess &&
               hipMalloc(&ctx->raw_err, sizeof(int)) == hipSuccess &&
@@ -266,7 +273,7 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
               hipMalloc(&ctx->scratchB, (size_t)ctx->ncell * sizeof(double)) == hipSuccess &&
               hipMalloc(&ctx->partials, (size_t)totals_nparts(ctx->ncell) * 4 * sizeof(double) + 64) == hipSuccess &&
               hipMalloc(&ctx->norms_scratch, 16 * sizeof(double)) == hipSuccess &&
-              hipHostMalloc((void**)&ctx->host, 48 * sizeof(double)) == hipSuccess &&
+              hipHostMalloc((void**)&ctx->host, (kHostAux + kSlot + 16) * sizeof(double)) == hipSuccess &&
               hipHostMalloc((void**)&ctx->host_u, 4 * sizeof(unsigned long long)) == hipSuccess;
     if (ok && cfg->retarget_every == 0) {
         // adjoint scratch only for frozen-speed contexts (the raw entry points)
@@ -309,8 +316,8 @@ vlbm_status vlbm_init(vlbm_ctx* ctx, const double* W0, int32_t W0_on_device)
     HIPCHK(ctx, hipMemcpyAsync(ctx->scratchW, W0, wbytes,
                                W0_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, launch_reset_ctl(ctx->ring, ctx->stop_at, ctx->err, ctx->stream));
-    HIPCHK(ctx, launch_init(ctx->kp, ctx->fp32, ctx->scratchW, ctx->ncell, ctx->ring, ctx->err,
-                            ctx->cfg.retarget_every == 0, ctx->f[0], ctx->stream));
+    HIPCHK(ctx, launch_init(ctx->kp, ctx->fp32, ctx->scratchW, ctx->ncell, ctx->ring, ctx->ring + kRedBase,
+                            kRedCopies, kRedStride, ctx->err, ctx->cfg.retarget_every == 0, ctx->f[0], ctx->stream));
     vlbm_status st = sync_readback(ctx);
     if (st != VLBM_OK) return st;
     int bits;
@@ -374,10 +381,11 @@ vlbm_status vlbm_conserved_totals(vlbm_ctx* ctx, double* out)
     double* dout = ctx->norms_scratch;
     HIPCHK(ctx, launch_totals(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, ctx->kp.e_off, ctx->f[ctx->n & 1], ctx->partials, dout,
                               ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->host + 24, dout, ctx->NK * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host + kHostAux, dout, ctx->NK * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     const double vol = ctx->D == 1 ? ctx->cfg.dx : ctx->cfg.dx * ctx->cfg.dx;
-    for (int k = 0; k < ctx->NK; ++k) out[k] = ctx->host[24 + k] * vol;
+    for (int k = 0; k < ctx->NK; ++k) out[k] = ctx->host[kHostAux + k] * vol;
     return VLBM_OK;
 }
 
@@ -401,9 +409,11 @@ vlbm_status vlbm_get_beta(vlbm_ctx* ctx, double* out, int32_t out_on_device)
     KParams p = ctx->kp;
     p.c_fixed = ctx->c;
     KStep s{};
-    double* slot = ctx->ring + 8 * (ctx->n % 3);
+    double* slot = ctx->ring + kSlot * (ctx->n % 3);
     s.clock_in = slot;
-    s.red_in = slot + 2;
+    s.red_in = slot + kRedBase;
+    s.red_copies = kRedCopies;
+    s.red_stride = kRedStride;
     s.red_out = ctx->norms_scratch;
     s.err = ctx->raw_err;
     s.frozen = 1;
@@ -450,7 +460,7 @@ vlbm_status vlbm_get_clock(vlbm_ctx* ctx, double* t, double* c, int64_t* n)
 size_t vlbm_state_bytes(const vlbm_ctx* ctx)
 {
     if (!ctx) return 0;
-    return (size_t)ctx->nplanes * ctx->plane * ctx->esize + 32 * sizeof(double);
+    return (size_t)ctx->nplanes * ctx->plane * ctx->esize + (kSlot + 8) * sizeof(double);
 }
 
 vlbm_status vlbm_save(vlbm_ctx* ctx, void* buf)
@@ -460,10 +470,10 @@ vlbm_status vlbm_save(vlbm_ctx* ctx, void* buf)
     const size_t fb = (size_t)ctx->nplanes * ctx->plane * ctx->esize;
     HIPCHK(ctx, hipMemcpyAsync(buf, ctx->f[ctx->n & 1], fb, hipMemcpyDeviceToDevice, ctx->stream));
     // the current slot (clock + reductions of the state) and the step count
-    HIPCHK(ctx, hipMemcpyAsync((char*)buf + fb, ctx->ring + 8 * (ctx->n % 3), 8 * sizeof(double),
+    HIPCHK(ctx, hipMemcpyAsync((char*)buf + fb, ctx->ring + kSlot * (ctx->n % 3), kSlot * sizeof(double),
                                hipMemcpyDeviceToDevice, ctx->stream));
-    ctx->host[24] = (double)ctx->n;
-    HIPCHK(ctx, hipMemcpyAsync((char*)buf + fb + 8 * sizeof(double), ctx->host + 24, sizeof(double),
+    ctx->host[kHostAux] = (double)ctx->n;
+    HIPCHK(ctx, hipMemcpyAsync((char*)buf + fb + kSlot * sizeof(double), ctx->host + kHostAux, sizeof(double),
                                hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return VLBM_OK;
@@ -473,19 +483,19 @@ vlbm_status vlbm_restore(vlbm_ctx* ctx, const void* buf)
 {
     if (!ctx || !buf) return fail(ctx, VLBM_EINVAL, "null argument");
     const size_t fb = (size_t)ctx->nplanes * ctx->plane * ctx->esize;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->host + 24, (const char*)buf + fb, 9 * sizeof(double), hipMemcpyDeviceToHost,
-                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host + kHostAux, (const char*)buf + fb, (kSlot + 1) * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    const long long n = (long long)ctx->host[32];
+    const long long n = (long long)ctx->host[kHostAux + kSlot];
     if (n < 0) return fail(ctx, VLBM_EINVAL, "corrupt checkpoint");
     HIPCHK(ctx, launch_reset_ctl(ctx->ring, ctx->stop_at, ctx->err, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(ctx->f[n & 1], buf, fb, hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->ring + 8 * (n % 3), (const char*)buf + fb, 8 * sizeof(double),
+    HIPCHK(ctx, hipMemcpyAsync(ctx->ring + kSlot * (n % 3), (const char*)buf + fb, kSlot * sizeof(double),
                                hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->n = n;
-    ctx->t = ctx->host[24];
-    ctx->c = ctx->host[25];
+    ctx->t = ctx->host[kHostAux];
+    ctx->c = ctx->host[kHostAux + 1];
     ctx->initialised = true;
     return VLBM_OK;
 }
@@ -518,8 +528,8 @@ vlbm_status vlbm_raw_init(vlbm_ctx* ctx, const double* W0, void* f0, double* nor
     if (vlbm_status st = need_frozen(ctx)) return st;
     if (!W0 || !f0 || !norms0) return fail(ctx, VLBM_EINVAL, "null argument");
     HIPCHK(ctx, launch_zero(ctx->norms_scratch, 8, ctx->stream));
-    HIPCHK(ctx, launch_init(ctx->kp, ctx->fp32, W0, ctx->ncell, ctx->norms_scratch, ctx->raw_err, 1, f0,
-                            ctx->stream));
+    HIPCHK(ctx, launch_init(ctx->kp, ctx->fp32, W0, ctx->ncell, ctx->norms_scratch, ctx->norms_scratch + 2, 1, 0,
+                            ctx->raw_err, 1, f0, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(norms0, ctx->norms_scratch + 2, (ctx->NK + 1) * sizeof(double),
                                hipMemcpyDeviceToDevice, ctx->stream));
     return VLBM_OK;

@@ -3,12 +3,14 @@
 // moments and layout copies.
 #include "vlbm_aux.hpp"
 
+#include <algorithm>
+
 namespace vlbm {
 
 __global__ void k_reset_ctl(double* ring, unsigned long long* stop_at, int* err)
 {
     const int i = threadIdx.x;
-    if (i < 24) ring[i] = 0.0;
+    for (int j = i; j < 3 * kSlot; j += blockDim.x) ring[j] = 0.0;
     if (i == 0) {
         *stop_at = ~0ull;
         *err = 0;
@@ -46,10 +48,11 @@ __device__ __forceinline__ void prim_cell(const Gas<double>& g, int D, const dou
     P = eos_pressure<double, EOS>(g, rho, e);
 }
 
-// Reductions of the initial state: s_max (Eq. 36) and M_k (Eq. 30) into
-// red_out[0], red_out[1 + k]; admissibility bits into err.
+// Reductions of the initial state: s_max (Eq. 36) and M_k (Eq. 30) into the
+// `copies` copies at red_out (stride doubles apart); admissibility bits into err.
 template <int EOS>
-__global__ void k_init_reduce(KParams p, const double* __restrict__ W, long long ncell, double* red_out, int* err)
+__global__ void __launch_bounds__(256) k_init_reduce(KParams p, const double* __restrict__ W, long long ncell,
+                                                     double* red_out, int copies, int stride, int* err)
 {
     const Gas<double> g = make_gas<double>(p);
     const int D = p.dim;
@@ -72,21 +75,25 @@ __global__ void k_init_reduce(KParams p, const double* __restrict__ W, long long
     }
     KStep s{};
     s.red_out = red_out;
+    s.red_copies = copies;
+    s.red_stride = stride;
     s.err = err;
-    wave_publish(s, smax, M, D + 2, bits);
+    block_publish<4>(s, smax, M, D + 2, bits);
 }
 
-// f = f^eq(W0; c0) (Eq. 20); c0 = s_max/CFL from red (or c_fixed).  Block 0
-// writes the clock (t = 0, c0) of slot 0.  The energy component is stored in
+// f = f^eq(W0; c0) (Eq. 20); c0 = s_max/CFL from the reductions of W0 (or
+// c_fixed).  Block 0 writes the clock (t = 0, c0) to clock0.  The energy component is stored in
 // the shifted gauge: W_E - e_off W_rho and Q_E - e_off Q_rho (linear in W, Q).
 template <typename T, int EOS>
-__global__ void k_init_eq(KParams p, const double* __restrict__ W, long long ncell, double* slot0, int frozen,
-                          T* __restrict__ f)
+__global__ void k_init_eq(KParams p, const double* __restrict__ W, long long ncell, double* clock0,
+                          const double* red0, int copies, int stride, int frozen, T* __restrict__ f)
 {
-    const double c0 = frozen ? p.c_fixed : slot0[2] / p.cfl;
+    double smax = red0[0];
+    for (int i = 1; i < copies; ++i) smax = fmax(smax, red0[i * stride]);
+    const double c0 = frozen ? p.c_fixed : smax / p.cfl;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        slot0[0] = 0.0;
-        slot0[1] = c0;
+        clock0[0] = 0.0;
+        clock0[1] = c0;
     }
     const Gas<double> g = make_gas<double>(p);
     const int D = p.dim, NK = D + 2;
@@ -224,7 +231,7 @@ static unsigned grid_for(long long n, int block)
 
 hipError_t launch_reset_ctl(double* ring, unsigned long long* stop_at, int* err, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, st, ring, stop_at, err);
+    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(256), 0, st, ring, stop_at, err);
     return hipGetLastError();
 }
 
@@ -240,34 +247,31 @@ hipError_t launch_zero(double* p, int n, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_init(const KParams& p, bool fp32, const double* W, long long ncell, double* slot0, int* err,
-                       int frozen, void* f, hipStream_t st)
+// the reduction kernels stride over the cells with few blocks: one set of
+// same-address atomics per block
+static unsigned reduce_grid(long long ncell) { return std::min(grid_for(ncell, 256), 1024u); }
+
+hipError_t launch_init(const KParams& p, bool fp32, const double* W, long long ncell, double* clock0, double* red0,
+                       int copies, int stride, int* err, int frozen, void* f, hipStream_t st)
 {
     const unsigned grid = grid_for(ncell, 256);
     if (p.eos == 0)
-        hipLaunchKernelGGL(k_init_reduce<0>, dim3(grid), dim3(256), 0, st, p, W, ncell, slot0 + 2, err);
+        hipLaunchKernelGGL(k_init_reduce<0>, dim3(reduce_grid(ncell)), dim3(256), 0, st, p, W, ncell, red0, copies,
+                           stride, err);
     else
-        hipLaunchKernelGGL(k_init_reduce<1>, dim3(grid), dim3(256), 0, st, p, W, ncell, slot0 + 2, err);
+        hipLaunchKernelGGL(k_init_reduce<1>, dim3(reduce_grid(ncell)), dim3(256), 0, st, p, W, ncell, red0, copies,
+                           stride, err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-#define VLBM_INIT(T, E) hipLaunchKernelGGL((k_init_eq<T, E>), dim3(grid), dim3(256), 0, st, p, W, ncell, slot0, frozen, (T*)f)
+#define VLBM_INIT(T, E)                                                                                   \
+    hipLaunchKernelGGL((k_init_eq<T, E>), dim3(grid), dim3(256), 0, st, p, W, ncell, clock0, (const double*)red0, \
+                       copies, stride, frozen, (T*)f)
     if (fp32) {
         if (p.eos == 0) VLBM_INIT(float, 0); else VLBM_INIT(float, 1);
     } else {
         if (p.eos == 0) VLBM_INIT(double, 0); else VLBM_INIT(double, 1);
     }
 #undef VLBM_INIT
-    return hipGetLastError();
-}
-
-hipError_t launch_init_reduce_only(const KParams& p, const double* W, long long ncell, double* red_out, int* err,
-                                   hipStream_t st)
-{
-    const unsigned grid = grid_for(ncell, 256);
-    if (p.eos == 0)
-        hipLaunchKernelGGL(k_init_reduce<0>, dim3(grid), dim3(256), 0, st, p, W, ncell, red_out, err);
-    else
-        hipLaunchKernelGGL(k_init_reduce<1>, dim3(grid), dim3(256), 0, st, p, W, ncell, red_out, err);
     return hipGetLastError();
 }
 

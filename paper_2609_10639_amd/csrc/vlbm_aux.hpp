@@ -12,10 +12,10 @@ int step_d2q4_blocks_per_cu(const KParams& p, int prec);
 hipError_t launch_reset_ctl(double* ring, unsigned long long* stop_at, int* err, hipStream_t st);
 hipError_t launch_reset_stop(unsigned long long* stop_at, int* err, hipStream_t st);
 hipError_t launch_zero(double* p, int n, hipStream_t st);
-hipError_t launch_init(const KParams& p, bool fp32, const double* W, long long ncell, double* slot0, int* err,
-                       int frozen, void* f, hipStream_t st);
-hipError_t launch_init_reduce_only(const KParams& p, const double* W, long long ncell, double* red_out, int* err,
-                                   hipStream_t st);
+// reductions of W0 into `copies` copies at red0 (stride apart), then the clock
+// (t = 0, c0) at clock0 and f = f^eq(W0; c0)
+hipError_t launch_init(const KParams& p, bool fp32, const double* W, long long ncell, double* clock0, double* red0,
+                       int copies, int stride, int* err, int frozen, void* f, hipStream_t st);
 // moments, totals and the population copy return the physical energy gauge
 // (e_off: the gauge shift of the stored populations, KParams::e_off)
 hipError_t launch_moments(int D, long long plane, long long ncell, bool fp32, double e_off, const void* f, double* W,

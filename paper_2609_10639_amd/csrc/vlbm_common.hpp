@@ -27,15 +27,29 @@ struct KParams {
 // Per-launch control: where the clock and the reductions of the current state
 // are read from and where those of the next state go.
 //
-// A ring slot is 8 doubles: [0] t, [1] c, [2] s_max, [3 + k] max|Q_alpha,k|.
-// Step n reads slot n%3, writes the clock and accumulates the reductions of the
-// new state into slot (n+1)%3, and clears the reductions of slot (n+2)%3.
+// Reductions (s_max, then max|Q_alpha,k| for each component k) are kept in
+// `red_copies` copies, `red_stride` doubles apart: a workgroup publishes its
+// maxima into copy blockIdx % red_copies and readers take the maximum over the
+// copies (exact and order-free).  Spreading the atomics over copies on
+// separate cache lines keeps same-address atomics from serialising at the end
+// of a launch.  red_copies <= 1 means one copy.
+//
+// Ring slot (kSlot doubles): [0] t, [1] c, copy i of the reductions at
+// kRedBase + i kRedStride.  Step n reads slot n%3, writes the clock and
+// accumulates the reductions of the new state into slot (n+1)%3, and clears
+// the reductions of slot (n+2)%3.
+constexpr int kRedCopies = 16, kRedStride = 16, kRedBase = 16;
+constexpr int kSlot = kRedBase + kRedCopies * kRedStride;
+constexpr int kRedFields = 6;      // s_max and up to 4 components, plus one spare
+
 struct KStep {
     const double* clock_in;        // t, c of the current state
     double* clock_out;             // t, c after the step (block 0 writes)
-    const double* red_in;          // s_max, M_k of the current state
-    double* red_out;               // s_max, M_k of the new state (atomic max)
-    double* red_clear;             // reductions to zero (nullable)
+    const double* red_in;          // s_max, M_k of the current state (copy 0)
+    double* red_out;               // s_max, M_k of the new state (atomic max, copy 0)
+    double* red_clear;             // reductions to zero (copy 0, nullable)
+    int red_copies;                // copies of the three reduction blocks
+    int red_stride;                // doubles between copies
     unsigned long long* stop_at;   // steps with n >= *stop_at return at once (nullable)
     int* err;                      // error bits (1: non-hyperbolic, 2: non-finite)
     long long n;                   // index of this step
@@ -142,6 +156,28 @@ __device__ __forceinline__ int eos_check(const Gas<T>& g, T rho, T e, T cs2)
     return bits;
 }
 
+// maximum over the copies of reduction field j of the current state
+__device__ __forceinline__ double red_fold(const KStep& s, int j)
+{
+    double v = s.red_in[j];
+    for (int i = 1; i < s.red_copies; ++i) v = fmax(v, s.red_in[i * s.red_stride + j]);
+    return v;
+}
+
+// the copy of the new state's reductions this workgroup publishes into
+__device__ __forceinline__ double* red_target(const KStep& s)
+{
+    return s.red_copies > 1 ? s.red_out + (int)(blockIdx.x % (unsigned)s.red_copies) * s.red_stride : s.red_out;
+}
+
+// zero every copy of the reductions two steps ahead; lanes of one wave
+__device__ __forceinline__ void clear_reductions(const KStep& s, int lane)
+{
+    if (!s.red_clear) return;
+    const int copies = s.red_copies > 1 ? s.red_copies : 1;
+    for (int i = lane; i < copies * kRedFields; i += 64) s.red_clear[(i / kRedFields) * s.red_stride + i % kRedFields] = 0.0;
+}
+
 // Clock logic of one step (Sec. III.E): retarget c = s_max/CFL (Eq. 37), dt =
 // dx/c, final-step landing.  Returns false when the step must not run.
 __device__ __forceinline__ bool step_clock(const KParams& p, const KStep& s, double& c_old,
@@ -157,7 +193,7 @@ __device__ __forceinline__ bool step_clock(const KParams& p, const KStep& s, dou
     if (s.stop_at && (unsigned long long)s.n >= *s.stop_at) return false;
     t = s.clock_in[0];
     c_old = s.clock_in[1];
-    const double smax = s.red_in[0];
+    const double smax = red_fold(s, 0);
     c_new = c_old;
     if (p.retarget_every > 0 && ((s.n % p.retarget_every) == 0 || smax > c_old)) c_new = smax / p.cfl;
     dt = p.dx / c_new;
@@ -175,8 +211,6 @@ __device__ __forceinline__ void write_clock(const KStep& s, double t, double dt,
     s.clock_out[0] = last ? s.t_end : t + dt;
     s.clock_out[1] = c_new;
     if (last) atomicMin(s.stop_at, (unsigned long long)(s.n + 1));
-    if (s.red_clear)
-        for (int j = 0; j < 6; ++j) s.red_clear[j] = 0.0;
 }
 
 // Max of non-negative doubles through their IEEE bit patterns (monotone as
@@ -210,10 +244,45 @@ __device__ __forceinline__ void wave_publish(const KStep& s, double smax, const 
     for (int k = 0; k < nk; ++k) Mr[k] = wave_max(M[k]);
     errbits = wave_or(errbits);
     if ((threadIdx.x & 63) == 0) {
-        atomic_max_nonneg(&s.red_out[0], smax);
-        for (int k = 0; k < nk; ++k) atomic_max_nonneg(&s.red_out[1 + k], Mr[k]);
+        double* out = red_target(s);
+        atomic_max_nonneg(&out[0], smax);
+        for (int k = 0; k < nk; ++k) atomic_max_nonneg(&out[1 + k], Mr[k]);
         if (errbits) {
             atomicOr(s.err, errbits);
+            if (s.stop_at) atomicMin(s.stop_at, (unsigned long long)(s.n + 1));
+        }
+    }
+}
+
+// Publish the per-lane maxima of a whole block of NW waves with one set of
+// atomics per block (same-address atomics serialise in L2, so a launch issues
+// as few as it can).  Call with every thread of the block.
+template <int NW>
+__device__ __forceinline__ void block_publish(const KStep& s, double smax, const double* M, int nk, int errbits)
+{
+    __shared__ double sh[NW][5];
+    __shared__ int she[NW];
+    smax = wave_max(smax);
+    double Mr[4] = {0, 0, 0, 0};
+    for (int k = 0; k < nk; ++k) Mr[k] = wave_max(M[k]);
+    errbits = wave_or(errbits);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w][0] = smax;
+        for (int k = 0; k < 4; ++k) sh[w][1 + k] = Mr[k];
+        she[w] = errbits;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < NW; ++i) {
+            for (int k = 0; k < 5; ++k) sh[0][k] = fmax(sh[0][k], sh[i][k]);
+            she[0] |= she[i];
+        }
+        double* out = red_target(s);
+        atomic_max_nonneg(&out[0], sh[0][0]);
+        for (int k = 0; k < nk; ++k) atomic_max_nonneg(&out[1 + k], sh[0][1 + k]);
+        if (she[0]) {
+            atomicOr(s.err, she[0]);
             if (s.stop_at) atomicMin(s.stop_at, (unsigned long long)(s.n + 1));
         }
     }

@@ -1,8 +1,8 @@
 // Fused D1Q2 VLBM time step for gfx950 (arXiv 2609.10639, Sec. III).
 //
-// A 256-thread workgroup owns 256 consecutive cells.  It stages the 262 cells
-// of its tile plus a 3-cell halo in LDS and runs the step in four
-// barrier-separated phases:
+// A 256-thread workgroup processes tiles of 256 consecutive cells (grid-stride
+// over the tiles, at most 1024 workgroups).  It stages the 262 cells of a tile
+// plus a 3-cell halo in LDS and runs the step in four barrier-separated phases:
 //   A  load the 6 populations (SoA planes, coalesced), reproject to the new
 //      link speed (Sec. III.E, D = 1 form of Eq. 40), flux Q(W) (Eq. 10);
 //   B  normalised flux-divergence activity s (Eqs. 28-31);
@@ -15,6 +15,7 @@ namespace vlbm {
 constexpr int kTile1 = 256;
 constexpr int kHalo1 = 3;
 constexpr int kSlots1 = kTile1 + 2 * kHalo1;
+constexpr int kGrid1 = 1024;   // blocks per launch (4 per CU); each strides over the tiles
 
 template <typename ST, typename T, int EOS, int SENSOR>
 __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep S, const ST* __restrict__ fin,
@@ -29,6 +30,7 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
     bool last;
     if (!step_clock(P, S, c_old, c_new, t, dt, last)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) write_clock(S, t, dt, c_new, last);
+    if (blockIdx.x == 0 && threadIdx.x < 64 && !S.frozen) clear_reductions(S, threadIdx.x);
 
     const Gas<T> g = make_gas<T>(P);
     const bool reproj = (c_old != c_new);
@@ -38,126 +40,133 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
     T invM[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double M = S.red_in[1 + k];
+        const double M = red_fold(S, 1 + k);
         invM[k] = M > 0.0 ? (T)(1.0 / M) : (T)0;
     }
     const int nx = P.nx;
     const long long plane = P.plane;
-    const int x0 = blockIdx.x * kTile1;
     const bool cl = P.bc[0] == 1, ch = P.bc[1] == 1;
+    const int ntiles = (nx + kTile1 - 1) / kTile1;
 
-    // slot s holds cell X = x0 - 3 + s; neighbour slots follow the boundary rule
-    auto cell_of = [&](int X) {
-        if (X < 0) return cl ? 0 : wrap_index(X, nx);
-        if (X >= nx) return ch ? nx - 1 : wrap_index(X, nx);
-        return X;
-    };
-    auto left_of = [&](int s) { return (cl && x0 - kHalo1 + s == 0) ? s : s - 1; };
-    auto right_of = [&](int s) { return (ch && x0 - kHalo1 + s == nx - 1) ? s : s + 1; };
-
-    // ---- A
-    for (int s = threadIdx.x; s < kSlots1; s += kTile1) {
-        const int cx = cell_of(x0 - kHalo1 + s);
-        T f[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) f[j] = (T)fin[j * plane + cx];
-        if (reproj) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const T sm = f[k] + f[3 + k], df = f[k] - f[3 + k];
-                const T a = (T)0.5 * sm, b = (T)0.5 * r * df;
-                f[k] = a + b;
-                f[3 + k] = a - b;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 6; ++j) sf[j][s] = f[j];
-        const T rho = f[0] + f[3], m = f[1] + f[4], E = f[2] + f[5];
-        const T u = m / rho;
-        const T e = E / rho - (T)0.5 * u * u + eoff;
-        const T Pp = eos_pressure<T, EOS>(g, rho, e);
-        sq[0][s] = m;
-        sq[1][s] = m * u + Pp;
-        sq[2][s] = (E + Pp) * u;
-    }
-    __syncthreads();
-    // ---- B
-    if constexpr (SENSOR != 0) {
-        for (int s = threadIdx.x + 1; s < kSlots1 - 1; s += kTile1) {
-            const int sl = left_of(s), sr = right_of(s);
-            T acc = 0, j0 = 0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                T jk = (T)0.5 * (sq[k][sr] - sq[k][sl]);
-                if (k == 0) j0 = jk;
-                if (k == 2) jk = fma(eoff, j0, jk);   // physical energy flux: Q_E,stored + eoff Q_rho
-                const T sh = jk * invM[k];
-                acc += sh * sh;
-            }
-            sa[s] = sqrt(acc / (T)3);
-        }
-        __syncthreads();
-    }
-    // ---- C
-    for (int s = threadIdx.x + 2; s < kSlots1 - 2; s += kTile1) {
-        T beta = (T)P.beta_const;
-        if constexpr (SENSOR != 0) {
-            const T sbar = (T)0.25 * sa[left_of(s)] + (T)0.5 * sa[s] + (T)0.25 * sa[right_of(s)];
-            T chiv = (T)P.c_sensor * sbar;
-            chiv = chiv < (T)0 ? (T)0 : (chiv > (T)1 ? (T)1 : chiv);
-            beta = (T)P.beta_max - (T)(P.beta_max - P.beta_min) * chiv;
-        }
-        const int X = x0 - kHalo1 + s;
-        if (S.probe) {
-            if (s >= kHalo1 && s < kHalo1 + kTile1 && X < nx) S.beta_out[X] = (double)beta;
-            continue;
-        }
-        const T tb = (T)2 * beta;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T w2 = (T)0.5 * (sf[k][s] + sf[3 + k][s]);
-            const T a = sq[k][s] * inv2c;
-            sg[k][s] = sf[k][s] + tb * ((w2 + a) - sf[k][s]);
-            sg[3 + k][s] = sf[3 + k][s] + tb * ((w2 - a) - sf[3 + k][s]);
-        }
-    }
-    if (S.probe) return;
-    __syncthreads();
-    // ---- D
+    // reductions of the new state over every tile this block visits
     double red_s = 0.0, red_M[3] = {0.0, 0.0, 0.0};
     int errbits = 0;
-    {
-        const int s = kHalo1 + threadIdx.x;
-        const int X = x0 + threadIdx.x;
-        if (X < nx) {
-            const int sl = left_of(s), sr = right_of(s);
-            T gn[6];
+
+    // grid-stride over tiles of kTile1 cells: few blocks, one set of atomics each
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int x0 = tile * kTile1;
+        // slot s holds cell X = x0 - 3 + s; neighbour slots follow the boundary rule
+        auto cell_of = [&](int X) {
+            if (X < 0) return cl ? 0 : wrap_index(X, nx);
+            if (X >= nx) return ch ? nx - 1 : wrap_index(X, nx);
+            return X;
+        };
+        auto left_of = [&](int s) { return (cl && x0 - kHalo1 + s == 0) ? s : s - 1; };
+        auto right_of = [&](int s) { return (ch && x0 - kHalo1 + s == nx - 1) ? s : s + 1; };
+
+        // ---- A
+        for (int s = threadIdx.x; s < kSlots1; s += kTile1) {
+            const int cx = cell_of(x0 - kHalo1 + s);
+            T f[6];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                gn[k] = sg[k][sl];
-                gn[3 + k] = sg[3 + k][sr];
+            for (int j = 0; j < 6; ++j) f[j] = (T)fin[j * plane + cx];
+            if (reproj) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const T sm = f[k] + f[3 + k], df = f[k] - f[3 + k];
+                    const T a = (T)0.5 * sm, b = (T)0.5 * r * df;
+                    f[k] = a + b;
+                    f[3 + k] = a - b;
+                }
             }
 #pragma unroll
-            for (int j = 0; j < 6; ++j) fout[j * plane + X] = (ST)gn[j];
-            const T rho = gn[0] + gn[3], m = gn[1] + gn[4], E = gn[2] + gn[5];
+            for (int j = 0; j < 6; ++j) sf[j][s] = f[j];
+            const T rho = f[0] + f[3], m = f[1] + f[4], E = f[2] + f[5];
             const T u = m / rho;
             const T e = E / rho - (T)0.5 * u * u + eoff;
             const T Pp = eos_pressure<T, EOS>(g, rho, e);
-            const T cs2 = eos_cs2<T, EOS>(g, rho, e);
-            errbits |= eos_check<T, EOS>(g, rho, e, cs2);
-            red_s = (double)(fabs(u) + sqrt(cs2 > (T)0 ? cs2 : (T)0));
-            red_M[0] = (double)fabs(m);
-            red_M[1] = (double)fabs(m * u + Pp);
-            red_M[2] = (double)fabs((fma(eoff, rho, E) + Pp) * u);
+            sq[0][s] = m;
+            sq[1][s] = m * u + Pp;
+            sq[2][s] = (E + Pp) * u;
         }
+        __syncthreads();
+        // ---- B
+        if constexpr (SENSOR != 0) {
+            for (int s = threadIdx.x + 1; s < kSlots1 - 1; s += kTile1) {
+                const int sl = left_of(s), sr = right_of(s);
+                T acc = 0, j0 = 0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    T jk = (T)0.5 * (sq[k][sr] - sq[k][sl]);
+                    if (k == 0) j0 = jk;
+                    if (k == 2) jk = fma(eoff, j0, jk);   // physical energy flux: Q_E,stored + eoff Q_rho
+                    const T sh = jk * invM[k];
+                    acc += sh * sh;
+                }
+                sa[s] = sqrt(acc / (T)3);
+            }
+            __syncthreads();
+        }
+        // ---- C
+        for (int s = threadIdx.x + 2; s < kSlots1 - 2; s += kTile1) {
+            T beta = (T)P.beta_const;
+            if constexpr (SENSOR != 0) {
+                const T sbar = (T)0.25 * sa[left_of(s)] + (T)0.5 * sa[s] + (T)0.25 * sa[right_of(s)];
+                T chiv = (T)P.c_sensor * sbar;
+                chiv = chiv < (T)0 ? (T)0 : (chiv > (T)1 ? (T)1 : chiv);
+                beta = (T)P.beta_max - (T)(P.beta_max - P.beta_min) * chiv;
+            }
+            const int X = x0 - kHalo1 + s;
+            if (S.probe) {
+                if (s >= kHalo1 && s < kHalo1 + kTile1 && X < nx) S.beta_out[X] = (double)beta;
+                continue;
+            }
+            const T tb = (T)2 * beta;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const T w2 = (T)0.5 * (sf[k][s] + sf[3 + k][s]);
+                const T a = sq[k][s] * inv2c;
+                sg[k][s] = sf[k][s] + tb * ((w2 + a) - sf[k][s]);
+                sg[3 + k][s] = sf[3 + k][s] + tb * ((w2 - a) - sf[3 + k][s]);
+            }
+        }
+        __syncthreads();
+        // ---- D
+        if (!S.probe) {
+            const int s = kHalo1 + threadIdx.x;
+            const int X = x0 + threadIdx.x;
+            if (X < nx) {
+                const int sl = left_of(s), sr = right_of(s);
+                T gn[6];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    gn[k] = sg[k][sl];
+                    gn[3 + k] = sg[3 + k][sr];
+                }
+#pragma unroll
+                for (int j = 0; j < 6; ++j) fout[j * plane + X] = (ST)gn[j];
+                const T rho = gn[0] + gn[3], m = gn[1] + gn[4], E = gn[2] + gn[5];
+                const T u = m / rho;
+                const T e = E / rho - (T)0.5 * u * u + eoff;
+                const T Pp = eos_pressure<T, EOS>(g, rho, e);
+                const T cs2 = eos_cs2<T, EOS>(g, rho, e);
+                errbits |= eos_check<T, EOS>(g, rho, e, cs2);
+                red_s = fmax(red_s, (double)(fabs(u) + sqrt(cs2 > (T)0 ? cs2 : (T)0)));
+                red_M[0] = fmax(red_M[0], (double)fabs(m));
+                red_M[1] = fmax(red_M[1], (double)fabs(m * u + Pp));
+                red_M[2] = fmax(red_M[2], (double)fabs((fma(eoff, rho, E) + Pp) * u));
+            }
+        }
+        __syncthreads();   // the next tile overwrites sf, sq, sa and sg
     }
-    wave_publish(S, red_s, red_M, 3, errbits);
+    if (!S.probe) block_publish<kTile1 / 64>(S, red_s, red_M, 3, errbits);
 }
 
 template <typename ST, typename T>
 static hipError_t launch_t(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
 {
-    const dim3 grid((p.nx + kTile1 - 1) / kTile1), block(kTile1);
+    const int ntiles = (p.nx + kTile1 - 1) / kTile1;
+    const dim3 grid(ntiles < kGrid1 ? ntiles : kGrid1), block(kTile1);
     const ST* in = (const ST*)fin;
     ST* out = (ST*)fout;
 #define VLBM_CASE(E, SN)                                                                      \

@@ -100,6 +100,7 @@ struct March {
     C J[3][4], Dl[3], Vo[3];   // partial sums of j_k, dilatation, vorticity
     C Ss[3], Sth[3];           // S_x[s], S_x[theta]
     C yprev[4], wpend[4];      // f*_{+y} of the last collided row, pending moments of the row below
+    S pre[16];                 // populations of the next row to enter the march (loads in flight)
     // reductions of the new state: maxima, and the admissibility witnesses
     C red_s, red_M[4], min_rho, min_cs2, min_gap, nan_acc;
 
@@ -122,20 +123,29 @@ struct March {
         red_M[3] = fmax(red_M[3], fmax(fabs(h * vx), fabs(h * vy)));
     }
 
-    // one row of the march; PH = (R - Rb) % 3
+    // issue the 16 population loads of row R (periodic rows wrap) into dst
+    __device__ __forceinline__ void load_row(int R, S* dst)
+    {
+        const int mrow = (R < 0 || R >= ny) ? wrap_index(R, ny) : R;
+        const unsigned off = ((unsigned)mrow * (unsigned)nx + colx) * (unsigned)sizeof(S);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dst[j] = bload(in, j, off, S());
+    }
+
+    // one row of the march; PH = (R - Rb) % 3.  Software-pipelined: the loads
+    // of row R+1 are in flight while row R is processed.
     template <int PH>
     __device__ __forceinline__ void iter(int R)
     {
         constexpr int cR = PH, cR1 = (PH + 2) % 3, cR2 = (PH + 1) % 3, cR3 = PH, cR4 = (PH + 2) % 3;
-        // ---------------- global loads of row R
+        // ---------------- row R arrived during the previous row; issue the loads of row R+1.
+        // The load is unconditional (past the last row it re-reads row Re, in bounds): a
+        // conditional load would merge into pre through copies that wait for the data at once.
         const bool hasA = R <= Re;
         S fa[16];
-        if (hasA) {
-            const int mrow = (R < 0 || R >= ny) ? wrap_index(R, ny) : R;
-            const unsigned off = ((unsigned)mrow * (unsigned)nx + colx) * (unsigned)sizeof(S);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) fa[j] = bload(in, j, off, S());
-        }
+        for (int j = 0; j < 16; ++j) fa[j] = pre[j];
+        load_row(min(R + 1, Re), pre);
 
         // ---------------- stage C: row p = R-3 (LDS slot cR3)
         const int p = R - 3;
@@ -321,6 +331,7 @@ __global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep S
     bool last;
     if (!step_clock(P, St, c_old, c_new, t, dt, last)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) write_clock(St, t, dt, c_new, last);
+    if (blockIdx.x == 0 && threadIdx.x < 64 && !St.frozen) clear_reductions(St, threadIdx.x);
 
     March<S, C, EOS, SENSOR> m{P, St};
     m.in = make_planes(fin, (unsigned)P.plane);
@@ -332,7 +343,7 @@ __global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep S
     m.inv2c = (C)(0.5 / c_new);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double M = St.red_in[1 + k];
+        const double M = red_fold(St, 1 + k);
         m.invM[k] = M > 0.0 ? (C)(1.0 / M) : (C)0;
     }
     m.inv2dx = (C)(0.5 / P.dx);
@@ -373,6 +384,7 @@ __global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep S
     m.min_rho = m.min_cs2 = m.min_gap = (C)1;
     m.nan_acc = (C)0;
 
+    if (m.Rb <= m.Re) m.load_row(m.Rb, m.pre);
     const int Rlast = m.y1 + 3;
     for (int R = m.Rb; R <= Rlast; R += 3) {
         m.template iter<0>(R);
