@@ -151,10 +151,14 @@ size_t vlbm_population_bytes(const vlbm_ctx* ctx);
 /* ---------------------------------------------------------------------------
  * Raw, stream-ordered entry points for differentiation with the link speed
  * frozen at c_fixed (retarget_every must be 0).  All pointers are device
- * pointers.  A population array uses the padded plane layout above; `norms`
- * arrays hold dim+3 doubles (s_max, then max_{x,alpha}|Q_alpha,k| for each
- * component k, Eq. 30) describing the state they belong to.
+ * pointers.  A population array uses the padded plane layout above.  A `norms`
+ * array (VLBM_NORMS_LEN doubles) describes the state it belongs to: 16 copies,
+ * 16 doubles apart, of (s_max, then max_{x,alpha}|Q_alpha,k| for each component
+ * k, Eq. 30); each quantity is the maximum over the copies (kernels spread
+ * their atomic maxima over the copies).  The caller allocates it; raw_init and
+ * raw_step overwrite their output array entirely.
  * ------------------------------------------------------------------------- */
+#define VLBM_NORMS_LEN 256
 
 /* f0 = f^eq(W0; c_fixed) (Eq. 20) and its norms.  W0: FP64 (dim+2, ny, nx). */
 vlbm_status vlbm_raw_init(vlbm_ctx* ctx, const double* W0, void* f0, double* norms0);

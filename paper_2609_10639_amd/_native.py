@@ -15,6 +15,7 @@ BC_PERIODIC, BC_OUTFLOW = 0, 1
 EOS_IDEAL, EOS_VDW = 0, 1
 SENSOR_OFF, SENSOR_A, SENSOR_B, SENSOR_AUTO = 0, 1, 2, 3
 FP64, FP32, FP32_MIXED = 0, 1, 2
+NORMS_LEN = 256   # doubles in a norms array (VLBM_NORMS_LEN)
 
 
 class VlbmConfig(ctypes.Structure):

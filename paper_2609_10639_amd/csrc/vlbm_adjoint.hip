@@ -152,6 +152,14 @@ struct AuxLayout {
     static constexpr int TOTAL = A4 + N4;
 };
 
+// maximum over the copies of field j of a norms array (kRedCopies copies, kRedStride apart)
+__device__ __forceinline__ double norm_max(const double* norms, int j)
+{
+    double v = norms[j];
+    for (int i = 1; i < kRedCopies; ++i) v = fmax(v, norms[i * kRedStride + j]);
+    return v;
+}
+
 template <typename S, typename C>
 __device__ __forceinline__ void load_cell(const S* f, long long plane, int Q, int NK, long long c, C* out)
 {
@@ -228,7 +236,10 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_p2(KParams p, const double* _
     const long long ncell = (long long)p.nx * p.ny;
     const C inv2dx = (C)(0.5 / p.dx);
     C invM[4];
-    for (int k = 0; k < NK; ++k) invM[k] = norms[1 + k] > 0.0 ? (C)(1.0 / norms[1 + k]) : (C)0;
+    for (int k = 0; k < NK; ++k) {
+        const double M = norm_max(norms, 1 + k);
+        invM[k] = M > 0.0 ? (C)(1.0 / M) : (C)0;
+    }
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
          c += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(c % p.nx), y = (int)(c / p.nx);
@@ -421,7 +432,10 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_p4(KParams p, const double* _
     const Geo<D> G = make_geo<D>(p);
     const long long ncell = (long long)p.nx * p.ny;
     C invM[4];
-    for (int k = 0; k < NK; ++k) invM[k] = norms[1 + k] > 0.0 ? (C)(1.0 / norms[1 + k]) : (C)0;
+    for (int k = 0; k < NK; ++k) {
+        const double M = norm_max(norms, 1 + k);
+        invM[k] = M > 0.0 ? (C)(1.0 / M) : (C)0;
+    }
     C mpart[4] = {0, 0, 0, 0};
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
          c += (long long)gridDim.x * blockDim.x) {

@@ -25,6 +25,8 @@
 
 using namespace vlbm;
 
+static_assert(kRedCopies * kRedStride == VLBM_NORMS_LEN, "norms arrays hold the reduction copies");
+
 // pinned host mirror: the three ring slots, then scratch for totals and checkpoints
 constexpr int kHostAux = 3 * kSlot;
 
@@ -527,11 +529,9 @@ vlbm_status vlbm_raw_init(vlbm_ctx* ctx, const double* W0, void* f0, double* nor
 {
     if (vlbm_status st = need_frozen(ctx)) return st;
     if (!W0 || !f0 || !norms0) return fail(ctx, VLBM_EINVAL, "null argument");
-    HIPCHK(ctx, launch_zero(ctx->norms_scratch, 8, ctx->stream));
-    HIPCHK(ctx, launch_init(ctx->kp, ctx->fp32, W0, ctx->ncell, ctx->norms_scratch, ctx->norms_scratch + 2, 1, 0,
+    HIPCHK(ctx, launch_zero(norms0, VLBM_NORMS_LEN, ctx->stream));
+    HIPCHK(ctx, launch_init(ctx->kp, ctx->fp32, W0, ctx->ncell, ctx->norms_scratch, norms0, kRedCopies, kRedStride,
                             ctx->raw_err, 1, f0, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(norms0, ctx->norms_scratch + 2, (ctx->NK + 1) * sizeof(double),
-                               hipMemcpyDeviceToDevice, ctx->stream));
     return VLBM_OK;
 }
 
@@ -539,10 +539,12 @@ vlbm_status vlbm_raw_step(vlbm_ctx* ctx, const void* f_in, const double* norms_i
 {
     if (vlbm_status st = need_frozen(ctx)) return st;
     if (!f_in || !f_out || !norms_in || !norms_out) return fail(ctx, VLBM_EINVAL, "null argument");
-    HIPCHK(ctx, launch_zero(norms_out, ctx->NK + 1, ctx->stream));
+    HIPCHK(ctx, launch_zero(norms_out, VLBM_NORMS_LEN, ctx->stream));
     KStep s{};
     s.red_in = norms_in;
     s.red_out = norms_out;
+    s.red_copies = kRedCopies;
+    s.red_stride = kRedStride;
     s.err = ctx->raw_err;
     s.frozen = 1;
     s.t_end = HUGE_VAL;

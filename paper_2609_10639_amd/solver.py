@@ -153,7 +153,7 @@ class Solver:
 
     def new_norms(self):
         torch = _torch()
-        return torch.zeros(self.D + 3, dtype=torch.float64, device="cuda")
+        return torch.zeros(N.NORMS_LEN, dtype=torch.float64, device="cuda")
 
     def raw_init(self, W0, f0, norms0):
         self._chk(N.lib().vlbm_raw_init(self._h, _ptr(W0), _ptr(f0), _ptr(norms0)))
