@@ -158,3 +158,14 @@ def misfit_gradient(cfg, W0, rho_target, nsteps):
     J = 0.5 * vol * ((WT[0] - torch.tensor(rho_target)) ** 2).sum()
     J.backward()
     return float(J.detach()), W.grad.numpy().copy(), WT.detach().numpy()
+
+
+def step_vjp(cfg, f, lam):
+    """lam^n = (d step / d f)^T lam for one frozen-speed step at the state f
+    (float64 numpy (Q, D+2, ny, nx) in and out)."""
+    import numpy as np
+    fr = Frozen(cfg)
+    ft = torch.tensor(np.asarray(f, dtype=np.float64), requires_grad=True)
+    out = fr.step(ft)
+    out.backward(torch.tensor(np.asarray(lam, dtype=np.float64)))
+    return ft.grad.numpy().copy()

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvlbm.so")
-SOURCES = ["vlbm_step2d.hip", "vlbm_step1d.hip", "vlbm_aux.hip", "vlbm_adjoint.hip", "vlbm_api.cpp"]
+SOURCES = ["vlbm_step2d.hip", "vlbm_step1d.hip", "vlbm_aux.hip", "vlbm_adjoint.hip", "vlbm_adjoint_march.hip",
+           "vlbm_api.cpp"]
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH,

@@ -1,0 +1,541 @@
+// Fused adjoint of one frozen-link-speed D2Q4 step (arXiv 2609.10639, Sec. III
+// with c fixed), in a single march over the rows.
+//
+// Forward map f^n -> f^{n+1} (c fixed, so no reprojection):
+//   W = sum_i f_i; closure and flux Q_alpha(W) (Eq. 10);
+//   j_k = 1/2 sum_alpha [Q_alpha,k(x+e_alpha) - Q_alpha,k(x-e_alpha)],
+//   s = sqrt(sum_k (j_k/M_k)^2 / 4), theta = dil^2/(dil^2 + vort^2 + eps),
+//   s-bar, theta-bar by the separable (1/4, 1/2, 1/4) filter, X = C s-bar theta-bar,
+//   beta = beta_max - (beta_max - beta_min) clip(X, 0, 1) (Eqs. 28-35);
+//   f*_i = f_i + beta g_i with g_i = 2 (f^eq_i - f_i) (Eqs. 20, 22);
+//   f^{n+1}_i(x) = f*_i(x - e_i) (Eq. 21; periodic wrap or clamped ghost).
+// Given lam = dJ/df^{n+1}, one wavefront owns a strip of columns and marches a
+// segment of rows; at row R it
+//   L  loads f(R) and lam(R); W, Q, u; g; the transposed streaming of lam
+//      (lam*_i(x) = sum of lam_i over the cells whose source is x) as far as it
+//      is known, accumulating dJ/dbeta = sum_i g_i lam*_i of rows R and R-1;
+//   A  accumulates the partial sums of j_k, dilatation and vorticity;
+//   B  completes s and theta of row R-1 and filters them along x;
+//   C  row R-2: beta and the seeds dJ/ds-bar = C theta-bar chi-bar,
+//      dJ/dtheta-bar = C s-bar chi-bar (chi-bar = -(beta_max - beta_min)
+//      dJ/dbeta where 0 < X < 1), the transposed x-filter, pushed into the
+//      transposed y-filter of rows R-3..R-1;
+//   D  row R-3: dJ/ds and dJ/dtheta complete -> dJ/dj_k, dJ/ddil, dJ/dvort,
+//      the normaliser adjoint (partial sums of dJ/dM_k), transposed central
+//      differences along x, pushed along y into rows R-4..R-2;
+//   E  row R-4: lam*(R-4) (re-read from cache), the direct equilibrium terms
+//      and the sensor terms through the closure transpose -> lam^n(R-4).
+// Each wavefront records its dJ/dM_k partial sums and the first maximiser of
+// every |Q_alpha,k| over its cells; k_adjm_fix folds the records and adds the
+// normaliser term at the maximisers.
+// Non-smooth points: d clip/dX = 1 on (0, 1), 0 elsewhere; d sqrt(s)/ds := 0 at
+// s = 0; the M_k sub-gradient goes to the first maximiser in (alpha, y, x) order.
+#include "vlbm_adjoint_math.hpp"
+#include "vlbm_aux.hpp"
+#include "vlbm_planes.hpp"
+
+namespace vlbm {
+
+constexpr int kRecDoubles = 12;   // per wavefront: dJ/dM_k (4), max |Q| (4), its cell index (4)
+
+template <typename S, typename C, int EOS, int SENSOR>
+struct AdjMarch {
+    const KParams& P;
+    Planes fin, lin, lout;      // f^n, lam^{n+1}, lam^n
+    C (*wr)[4][64];             // W of the last five rows (LDS ring)
+    Gas<C> g;
+    C inv2c, inv2dx, invM[4], csen, bspan, bmax, eps;
+    int nx, ny, y0, y1, Rb, Re;
+    long long ncell;
+    bool clo, chi;              // clamped y-low / y-high boundaries
+    int lane, lnb, rnb, X;
+    unsigned colx;
+    bool owner, atL, atR;       // atL / atR: the clamped first / last column
+
+    // sensor forward: partial sums of rows R+1 (n), R, R-1, R-2, R-3
+    C Jn[4], J0[4], J1[4], J2[4], J3[4];
+    C Dn, D0, D1, D2, D3, Vn, V0, V1, V2, V3;
+    C s2, s3, Ss2, Ss3, Th2, Th3;   // s and the x-filtered s, theta of rows R-2, R-3
+    // dJ/dbeta of rows R (partial), R-1, R-2; g_{+y} and lam_{-y} of row R-1
+    C bb0, bb1, bb2, gyp[4], lym[4];
+    C bq1, bq2;                 // beta of rows R-3, R-4
+    // transposed y-filter of the seeds: rows R-3, R-2, R-1
+    C SAm, SA0, SAp, TBm, TB0, TBp;
+    // transposed y-differences: rows R-4, R-3, R-2; x-parts of row R-4
+    C QYm[4], QY0[4], QYp[4], UXm, UX0, UXp, UYm, UY0, UYp;
+    C QXh[4], UXh, UYh;
+    double mbar[4];
+    C amax[4];
+    double aidx[4];
+
+    __device__ __forceinline__ bool row_ok(int r) const { return !(clo && r < 0) && !(chi && r > ny - 1); }
+    __device__ __forceinline__ unsigned row_off(int r) const
+    {
+        const int m = (r < 0 || r >= ny) ? wrap_index(r, ny) : r;
+        return ((unsigned)m * (unsigned)nx + colx) * (unsigned)sizeof(S);
+    }
+    // transposed central difference along x: sum_x a(x) ([nb(x,+1)=z] - [nb(x,-1)=z])
+    __device__ __forceinline__ C tdiff_x(C a) const
+    {
+        const C l = shfl(a, lane > 0 ? lane - 1 : 0), r = shfl(a, lane < 63 ? lane + 1 : 63);
+        return (atL ? -a : l) + (atR ? a : -r);
+    }
+    // transposed (1/4, 1/2, 1/4) filter along x
+    __device__ __forceinline__ C tbox_x(C a) const
+    {
+        const C l = shfl(a, lane > 0 ? lane - 1 : 0), r = shfl(a, lane < 63 ? lane + 1 : 63);
+        return (C)0.25 * (atL ? a : l) + (C)0.5 * a + (C)0.25 * (atR ? a : r);
+    }
+
+    __device__ __forceinline__ void iter(int R)
+    {
+        const bool rowR = R <= Re && row_ok(R);
+        // ================= L: row R
+        C qx[4] = {0, 0, 0, 0}, qy[4] = {0, 0, 0, 0}, ux = 0, uy = 0;
+        C gy_p[4] = {0, 0, 0, 0}, ly_m[4] = {0, 0, 0, 0};
+        bb0 = 0;
+        if (rowR) {
+            const unsigned off = row_off(R);
+            C fv[16], lv[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                fv[j] = (C)bload(fin, j, off, S());
+                lv[j] = (C)bload(lin, j, off, S());
+            }
+            C W[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) W[k] = (fv[k] + fv[4 + k]) + (fv[8 + k] + fv[12 + k]);
+            const int slot = (R - Rb) % 5;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) wr[slot][k][lane] = W[k];
+            const C irho = (C)1 / W[0];
+            ux = W[1] * irho;
+            uy = W[2] * irho;
+            const C e = W[3] * irho - (C)0.5 * (ux * ux + uy * uy);
+            const C Pp = eos_pressure<C, EOS>(g, W[0], e);
+            const C h = W[3] + Pp;
+            qx[0] = W[1]; qx[1] = W[1] * ux + Pp; qx[2] = W[1] * uy; qx[3] = h * ux;
+            qy[0] = W[2]; qy[1] = W[2] * ux; qy[2] = W[2] * uy + Pp; qy[3] = h * uy;
+            // first maximiser of |Q_alpha,k| over the cells this wavefront owns
+            if (owner && R >= y0 && R < y1) {
+                const double cidx = (double)R * (double)nx + (double)X;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const C vx = fabs(qx[k]), vy = fabs(qy[k]);
+                    if (vx > amax[k]) { amax[k] = vx; aidx[k] = cidx; }
+                    if (vy > amax[k] || (vy == amax[k] && (double)ncell + cidx < aidx[k])) {
+                        amax[k] = vy;
+                        aidx[k] = (double)ncell + cidx;
+                    }
+                }
+            }
+            if constexpr (SENSOR != 0) {
+                // g_i = 2 (f^eq_i - f_i); lam* along x from the neighbour columns
+                C bx = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const C w4 = (C)0.25 * W[k];
+                    const C gxp = (C)2 * (w4 + qx[k] * inv2c - fv[k]);
+                    const C gxm = (C)2 * (w4 - qx[k] * inv2c - fv[4 + k]);
+                    const C gyy = (C)2 * (w4 + qy[k] * inv2c - fv[8 + k]);
+                    const C gym = (C)2 * (w4 - qy[k] * inv2c - fv[12 + k]);
+                    const C lpr = shfl(lv[k], lane < 63 ? lane + 1 : 63);
+                    const C lml = shfl(lv[4 + k], lane > 0 ? lane - 1 : 0);
+                    const C lsxp = (atR ? (C)0 : lpr) + (atL ? lv[k] : (C)0);
+                    const C lsxm = (atL ? (C)0 : lml) + (atR ? lv[4 + k] : (C)0);
+                    bx += gxp * lsxp + gxm * lsxm;
+                    // lam*_{-y}(R) = lam_{-y}(R-1) [not below a clamped bottom] + lam_{-y}(R) at a clamped top
+                    const C lsym = ((clo && R == 0) ? (C)0 : lym[k]) + ((chi && R == ny - 1) ? lv[12 + k] : (C)0);
+                    bx += gym * lsym;
+                    // lam*_{+y}(R-1) = lam_{+y}(R) (+ lam_{+y}(0) itself when R-1 is a clamped bottom row)
+                    if (!(clo && R == 0)) bb1 += gyp[k] * lv[8 + k];
+                    if (clo && R == 0) bx += gyy * lv[8 + k];
+                    gy_p[k] = gyy;
+                    ly_m[k] = lv[12 + k];
+                }
+                bb0 = bx;
+            }
+        }
+
+        // ================= A: partial sums of j, dilatation, vorticity (row R)
+        if constexpr (SENSOR != 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Jn[k] = 0;
+            Dn = Vn = 0;
+            if (rowR) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const C hq = (C)0.5 * qy[k];
+                    J1[k] += hq;
+                    J0[k] += (C)0.5 * (shfl(qx[k], rnb) - shfl(qx[k], lnb));
+                    Jn[k] = -hq;
+                    if (clo && R == 0) J0[k] -= hq;
+                    if (chi && R == ny - 1) J0[k] += hq;
+                }
+                if constexpr (SENSOR == 2) {
+                    const C hx = ux * inv2dx, hy = uy * inv2dx;
+                    D1 += hy;
+                    V1 -= hx;
+                    D0 += (shfl(ux, rnb) - shfl(ux, lnb)) * inv2dx;
+                    V0 += (shfl(uy, rnb) - shfl(uy, lnb)) * inv2dx;
+                    Dn = -hy;
+                    Vn = hx;
+                    if (clo && R == 0) { D0 -= hy; V0 += hx; }
+                    if (chi && R == ny - 1) { D0 += hy; V0 -= hx; }
+                }
+            }
+        }
+
+        // ================= B: s, theta of row R-1, filtered along x
+        C s1 = 0, Ss1 = 0, Th1 = 0;
+        if constexpr (SENSOR != 0) {
+            if (row_ok(R - 1)) {
+                C acc = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const C sh = J1[k] * invM[k];
+                    acc = fma(sh, sh, acc);
+                }
+                s1 = acc > (C)0 ? sqrt(acc * (C)0.25) : (C)0;
+                Ss1 = (C)0.25 * shfl(s1, lnb) + (C)0.5 * s1 + (C)0.25 * shfl(s1, rnb);
+                if constexpr (SENSOR == 2) {
+                    const C d2 = D1 * D1;
+                    const C th = d2 / (fma(V1, V1, d2) + eps);
+                    Th1 = (C)0.25 * shfl(th, lnb) + (C)0.5 * th + (C)0.25 * shfl(th, rnb);
+                }
+            }
+        }
+
+        // ================= C: beta and the seeds of row p = R-2
+        C bnew = (C)P.beta_const;
+        if constexpr (SENSOR != 0) {
+            const int p = R - 2;
+            if (row_ok(p)) {
+                const C sm = (clo && p == 0) ? Ss2 : Ss3, sp = (chi && p == ny - 1) ? Ss2 : Ss1;
+                const C sbar = (C)0.25 * sm + (C)0.5 * Ss2 + (C)0.25 * sp;
+                C thbar = (C)1;
+                if constexpr (SENSOR == 2) {
+                    const C tm = (clo && p == 0) ? Th2 : Th3, tp = (chi && p == ny - 1) ? Th2 : Th1;
+                    thbar = (C)0.25 * tm + (C)0.5 * Th2 + (C)0.25 * tp;
+                }
+                const C Xv = csen * sbar * thbar;
+                const C chiv = fmin(fmax(Xv, (C)0), (C)1);
+                bnew = bmax - bspan * chiv;
+                const C chibar = (Xv > (C)0 && Xv < (C)1) ? -bspan * bb2 : (C)0;
+                const C ax = tbox_x(csen * thbar * chibar);
+                const bool pb = clo && p == 0, pt = chi && p == ny - 1;
+                const C qa = (C)0.25 * ax;
+                SAm += pb ? (C)0 : qa;
+                SA0 += (C)0.5 * ax + (pb ? qa : (C)0) + (pt ? qa : (C)0);
+                SAp += pt ? (C)0 : qa;
+                if constexpr (SENSOR == 2) {
+                    const C bx = tbox_x(csen * sbar * chibar);
+                    const C qb = (C)0.25 * bx;
+                    TBm += pb ? (C)0 : qb;
+                    TB0 += (C)0.5 * bx + (pb ? qb : (C)0) + (pt ? qb : (C)0);
+                    TBp += pt ? (C)0 : qb;
+                }
+            }
+        }
+
+        // ================= D: row q = R-3: dJ/dj, dJ/ddil, dJ/dvort; transposed differences
+        C QX[4] = {0, 0, 0, 0}, UXx = 0, UYx = 0;
+        if constexpr (SENSOR != 0) {
+            const int q = R - 3;
+            if (row_ok(q)) {
+                C jb[4] = {0, 0, 0, 0};
+                if (s3 > (C)0) {
+                    const C f4s = SAm / ((C)4 * s3);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const C shat = J3[k] * invM[k];
+                        const C shb = f4s * shat;   // d s / d s_hat_k = s_hat_k / (4 s)
+                        jb[k] = shb * invM[k];
+                        if (owner && q >= y0 && q < y1) mbar[k] -= (double)(shb * shat * invM[k]);
+                    }
+                }
+                C dilb = 0, vortb = 0;
+                if constexpr (SENSOR == 2) {
+                    const C den = D3 * D3 + V3 * V3 + eps;
+                    const C iden2 = (C)1 / (den * den);
+                    dilb = TBm * (C)2 * D3 * (V3 * V3 + eps) * iden2;
+                    vortb = -TBm * (C)2 * V3 * D3 * D3 * iden2;
+                }
+                const bool bot = clo && q == 0, top = chi && q == ny - 1;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    QX[k] = (C)0.5 * tdiff_x(jb[k]);
+                    const C hj = (C)0.5 * jb[k];
+                    QYp[k] += top ? (C)0 : hj;
+                    QY0[k] += (top ? hj : (C)0) - (bot ? hj : (C)0);
+                    QYm[k] -= bot ? (C)0 : hj;
+                }
+                if constexpr (SENSOR == 2) {
+                    // u_x-bar = (T_x dil-bar - T_y vort-bar)/(2dx), u_y-bar = (T_y dil-bar + T_x vort-bar)/(2dx)
+                    UXx = inv2dx * tdiff_x(dilb);
+                    UYx = inv2dx * tdiff_x(vortb);
+                    const C vx = -inv2dx * vortb, dy = inv2dx * dilb;
+                    UXp += top ? (C)0 : vx;
+                    UYp += top ? (C)0 : dy;
+                    UX0 += (top ? vx : (C)0) - (bot ? vx : (C)0);
+                    UY0 += (top ? dy : (C)0) - (bot ? dy : (C)0);
+                    UXm -= bot ? (C)0 : vx;
+                    UYm -= bot ? (C)0 : dy;
+                }
+            }
+        }
+
+        // ================= E: lam^n of row o = R-4
+        const int o = R - 4;
+        if (o >= y0 && o < y1 && row_ok(o)) {
+            const C beta = SENSOR != 0 ? bq2 : (C)P.beta_const;
+            const unsigned offo = row_off(o);
+            const bool bot = clo && o == 0, top = chi && o == ny - 1;
+            const unsigned offu = top ? offo : row_off(o + 1), offd = bot ? offo : row_off(o - 1);
+            C ls[16];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const C lp = (C)bload(lin, k, offo, S()), lm = (C)bload(lin, 4 + k, offo, S());
+                const C lpr = shfl(lp, lane < 63 ? lane + 1 : 63), lml = shfl(lm, lane > 0 ? lane - 1 : 0);
+                ls[k] = (atR ? (C)0 : lpr) + (atL ? lp : (C)0);
+                ls[4 + k] = (atL ? (C)0 : lml) + (atR ? lm : (C)0);
+                const C lyu = (C)bload(lin, 8 + k, offu, S()), lyd = (C)bload(lin, 12 + k, offd, S());
+                ls[8 + k] = top ? (C)0 : lyu;
+                ls[12 + k] = bot ? (C)0 : lyd;
+                if (bot) ls[8 + k] += (C)bload(lin, 8 + k, offo, S());
+                if (top) ls[12 + k] += (C)bload(lin, 12 + k, offo, S());
+            }
+            const int slot = (o - Rb) % 5;
+            C W[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) W[k] = wr[slot][k][lane];
+            const C tb = (C)2 * beta;
+            C Wb[4], Qb[2][4], ub[2];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                Wb[k] = tb * (C)0.25 * ((ls[k] + ls[4 + k]) + (ls[8 + k] + ls[12 + k]));
+                Qb[0][k] = tb * (ls[k] - ls[4 + k]) * inv2c + QXh[k];      // direct + x-differences of j-bar
+                Qb[1][k] = tb * (ls[8 + k] - ls[12 + k]) * inv2c + QYm[k]; // direct + y-differences of j-bar
+            }
+            ub[0] = UXh + UXm;
+            ub[1] = UYh + UYm;
+            closure_adj<C, EOS, 2>(g, W, Qb, ub, Wb);
+            if (owner) {
+                const C om = (C)1 - tb;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) bstore(lout, j, offo, (S)(om * ls[j] + Wb[j & 3]));
+            }
+        }
+
+        // ================= shift the row histories
+        if constexpr (SENSOR != 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                J3[k] = J2[k]; J2[k] = J1[k]; J1[k] = J0[k]; J0[k] = Jn[k];
+                QYm[k] = QY0[k]; QY0[k] = QYp[k]; QYp[k] = 0;
+                QXh[k] = QX[k];
+                gyp[k] = gy_p[k];
+                lym[k] = ly_m[k];
+            }
+            D3 = D2; D2 = D1; D1 = D0; D0 = Dn;
+            V3 = V2; V2 = V1; V1 = V0; V0 = Vn;
+            s3 = s2; s2 = s1;
+            Ss3 = Ss2; Ss2 = Ss1;
+            Th3 = Th2; Th2 = Th1;
+            bb2 = bb1; bb1 = bb0;
+            bq2 = bq1; bq1 = bnew;
+            SAm = SA0; SA0 = SAp; SAp = 0;
+            TBm = TB0; TB0 = TBp; TBp = 0;
+            UXm = UX0; UX0 = UXp; UXp = 0;
+            UYm = UY0; UY0 = UYp; UYp = 0;
+            UXh = UXx;
+            UYh = UYx;
+        }
+    }
+};
+
+template <typename S, typename C, int EOS, int SENSOR>
+__global__ void __launch_bounds__(64) k_adj_march(const KParams P, const S* __restrict__ f, const double* __restrict__ norms,
+                                                  const S* __restrict__ lam, S* __restrict__ lam_out,
+                                                  double* __restrict__ rec)
+{
+    __shared__ C wring[5][4][64];
+    AdjMarch<S, C, EOS, SENSOR> m{P};
+    m.fin = make_planes(f, (unsigned)P.plane);
+    m.lin = make_planes(lam, (unsigned)P.plane);
+    m.lout = make_planes((const S*)lam_out, (unsigned)P.plane);
+    m.wr = wring;
+    m.g = make_gas<C>(P);
+    m.inv2c = (C)(0.5 / P.c_fixed);
+    m.inv2dx = (C)(0.5 / P.dx);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double M = norms[1 + k];
+        for (int i = 1; i < kRedCopies; ++i) M = fmax(M, norms[i * kRedStride + 1 + k]);
+        m.invM[k] = M > 0.0 ? (C)(1.0 / M) : (C)0;
+    }
+    m.csen = (C)P.c_sensor;
+    m.bspan = (C)(P.beta_max - P.beta_min);
+    m.bmax = (C)P.beta_max;
+    m.eps = (C)P.eps_theta;
+    m.nx = P.nx;
+    m.ny = P.ny;
+    m.ncell = (long long)P.nx * P.ny;
+    m.lane = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int strip = tile % P.nstrips, seg = tile / P.nstrips;
+    const int halo = (64 - P.strip_w) / 2;
+    m.X = strip * P.strip_w - halo + m.lane;
+    int cx = m.X;
+    if (m.X < 0) cx = P.bc[0] == 0 ? wrap_index(m.X, m.nx) : 0;
+    else if (m.X >= m.nx) cx = P.bc[1] == 0 ? wrap_index(m.X, m.nx) : m.nx - 1;
+    m.colx = (unsigned)cx;
+    m.atL = P.bc[0] == 1 && m.X == 0;
+    m.atR = P.bc[1] == 1 && m.X == m.nx - 1;
+    m.lnb = m.atL ? m.lane : max(m.lane - 1, 0);
+    m.rnb = m.atR ? m.lane : min(m.lane + 1, 63);
+    m.owner = m.lane >= halo && m.lane < halo + P.strip_w && m.X < m.nx;
+    m.clo = P.bc[2] == 1;
+    m.chi = P.bc[3] == 1;
+    m.y0 = seg * P.seg_h;
+    m.y1 = min(m.y0 + P.seg_h, m.ny);
+    m.Rb = m.clo ? max(m.y0 - 4, 0) : m.y0 - 4;
+    m.Re = m.chi ? min(m.y1 + 3, m.ny - 1) : m.y1 + 3;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        m.Jn[k] = m.J0[k] = m.J1[k] = m.J2[k] = m.J3[k] = 0;
+        m.QYm[k] = m.QY0[k] = m.QYp[k] = m.QXh[k] = 0;
+        m.gyp[k] = m.lym[k] = 0;
+        m.mbar[k] = 0.0;
+        m.amax[k] = (C)-1;
+        m.aidx[k] = 0.0;
+    }
+    m.Dn = m.D0 = m.D1 = m.D2 = m.D3 = m.Vn = m.V0 = m.V1 = m.V2 = m.V3 = 0;
+    m.s2 = m.s3 = m.Ss2 = m.Ss3 = m.Th2 = m.Th3 = 0;
+    m.bb0 = m.bb1 = m.bb2 = 0;
+    m.bq1 = m.bq2 = (C)P.beta_const;
+    m.SAm = m.SA0 = m.SAp = m.TBm = m.TB0 = m.TBp = 0;
+    m.UXm = m.UX0 = m.UXp = m.UYm = m.UY0 = m.UYp = m.UXh = m.UYh = 0;
+
+    for (int R = m.Rb; R <= m.y1 + 3; ++R) m.iter(R);
+
+    // per-wavefront record: dJ/dM_k (sum over lanes, fixed tree), and the
+    // first maximiser of |Q_alpha,k| (largest value, then smallest index)
+    double* out = rec + (size_t)blockIdx.x * kRecDoubles;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double mb = m.mbar[k];
+        double v = (double)m.amax[k], ix = m.aidx[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            mb += __shfl_xor(mb, o, 64);
+            const double v2 = __shfl_xor(v, o, 64), i2 = __shfl_xor(ix, o, 64);
+            if (v2 > v || (v2 == v && i2 < ix)) { v = v2; ix = i2; }
+        }
+        if (m.lane == 0) {
+            out[k] = mb;
+            out[4 + k] = v;
+            out[8 + k] = ix;
+        }
+    }
+}
+
+// Folds the wavefront records (fixed order) and adds the normaliser term
+// dJ/dM_k * sign(Q_alpha,k) at the first maximiser of each |Q_alpha,k|,
+// through the closure transpose, to lam^n.  One workgroup.
+template <typename S, typename C, int EOS>
+__global__ void __launch_bounds__(256) k_adjm_fix(KParams p, const S* __restrict__ f, const double* __restrict__ rec,
+                                                  int nrec, S* __restrict__ lam_out)
+{
+    __shared__ double sm[4][256], sv[4][256], si[4][256];
+    double a[4] = {0, 0, 0, 0}, v[4] = {-1, -1, -1, -1}, ix[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nrec; b += 256)
+        for (int k = 0; k < 4; ++k) {
+            const double* r = rec + (size_t)b * kRecDoubles;
+            a[k] += r[k];
+            if (r[4 + k] > v[k] || (r[4 + k] == v[k] && r[8 + k] < ix[k])) {
+                v[k] = r[4 + k];
+                ix[k] = r[8 + k];
+            }
+        }
+    for (int k = 0; k < 4; ++k) {
+        sm[k][threadIdx.x] = a[k];
+        sv[k][threadIdx.x] = v[k];
+        si[k][threadIdx.x] = ix[k];
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 4; ++k) {
+                sm[k][threadIdx.x] += sm[k][threadIdx.x + s];
+                const double v2 = sv[k][threadIdx.x + s], i2 = si[k][threadIdx.x + s];
+                if (v2 > sv[k][threadIdx.x] || (v2 == sv[k][threadIdx.x] && i2 < si[k][threadIdx.x])) {
+                    sv[k][threadIdx.x] = v2;
+                    si[k][threadIdx.x] = i2;
+                }
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const long long ncell = (long long)p.nx * p.ny;
+    const Gas<C> g = make_gas<C>(p);
+    for (int k = 0; k < 4; ++k) {
+        const double Mb = sm[k][0];
+        if (Mb == 0.0 || sv[k][0] < 0.0) continue;
+        const long long id = (long long)si[k][0];
+        const int al = (int)(id / ncell);
+        const long long c = id % ncell;
+        C W[4] = {0, 0, 0, 0};
+        for (int i = 0; i < 4; ++i)
+            for (int kk = 0; kk < 4; ++kk) W[kk] += (C)f[(long long)(i * 4 + kk) * p.plane + c];
+        C u[2], e, P, Qf[2][4];
+        closure<C, EOS, 2>(g, W, u, e, P, Qf);
+        C Qb[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, ub[2] = {0, 0}, Wb[4] = {0, 0, 0, 0};
+        Qb[al][k] = (C)Mb * (Qf[al][k] > (C)0 ? (C)1 : (Qf[al][k] < (C)0 ? (C)-1 : (C)0));
+        closure_adj<C, EOS, 2>(g, W, Qb, ub, Wb);
+        for (int i = 0; i < 4; ++i)
+            for (int kk = 0; kk < 4; ++kk) {
+                S* dst = lam_out + (long long)(i * 4 + kk) * p.plane + c;
+                *dst = (S)((C)*dst + Wb[kk]);
+            }
+    }
+}
+
+int adjoint_march_records(const KParams& p) { return p.nstrips * p.nsegs; }
+
+bool adjoint_march_supported(const KParams& p)
+{
+    return p.dim == 2 && (64 - p.strip_w) / 2 >= 4 && p.e_off == 0.0;
+}
+
+template <typename S, typename C>
+static hipError_t march_t(const KParams& p, const void* f_n, const double* norms, const void* lam_np1, void* lam_n,
+                          double* rec, hipStream_t st)
+{
+    const int nb = adjoint_march_records(p);
+    const S* f = (const S*)f_n;
+    const S* lam = (const S*)lam_np1;
+    S* lo = (S*)lam_n;
+#define VLBM_AM(E, SN)                                                                                         \
+    if (p.eos == E && p.sensor == SN) {                                                                        \
+        hipLaunchKernelGGL((k_adj_march<S, C, E, SN>), dim3(nb), dim3(64), 0, st, p, f, norms, lam, lo, rec); \
+        if (SN != 0) hipLaunchKernelGGL((k_adjm_fix<S, C, E>), dim3(1), dim3(256), 0, st, p, f, rec, nb, lo);  \
+        return hipGetLastError();                                                                              \
+    }
+    VLBM_AM(0, 0) VLBM_AM(0, 1) VLBM_AM(0, 2) VLBM_AM(1, 0) VLBM_AM(1, 1) VLBM_AM(1, 2)
+#undef VLBM_AM
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint_march(const KParams& p, int prec, const void* f_n, const double* norms_n,
+                                const void* lam_np1, void* lam_n, double* rec, hipStream_t st)
+{
+    switch (prec) {
+    case PREC_FP64: return march_t<double, double>(p, f_n, norms_n, lam_np1, lam_n, rec, st);
+    case PREC_FP32: return march_t<float, float>(p, f_n, norms_n, lam_np1, lam_n, rec, st);
+    case PREC_FP32_MIXED: return march_t<float, double>(p, f_n, norms_n, lam_np1, lam_n, rec, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace vlbm

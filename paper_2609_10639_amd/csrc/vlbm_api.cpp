@@ -50,6 +50,7 @@ struct vlbm_ctx {
     unsigned long long* host_u = nullptr;
     int* raw_err = nullptr;
     AdjScratch adj{};
+    bool adj_march = false;        // fused single-march adjoint (D2Q4)
     hipStream_t stream;
     long long n = 0;
     double t = 0.0, c = 0.0;
@@ -282,7 +283,13 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
         ok = hipMalloc(&ctx->adj.aux, adjoint_aux_elems(p) * sizeof(double)) == hipSuccess &&
              hipMalloc(&ctx->adj.partials, adjoint_partials_count(p) * 4 * sizeof(double) + 64) == hipSuccess &&
              hipMalloc(&ctx->adj.qmax, 8 * sizeof(double)) == hipSuccess &&
-             hipMalloc(&ctx->adj.argmax, 8 * sizeof(unsigned long long)) == hipSuccess;
+             hipMalloc(&ctx->adj.argmax, 8 * sizeof(unsigned long long)) == hipSuccess &&
+             hipMalloc(&ctx->adj.rec, (size_t)std::max(adjoint_march_records(p), 1) * 12 * sizeof(double)) ==
+                 hipSuccess;
+        // the fused adjoint march is used where it applies (D2Q4, halo >= 4 columns,
+        // physical energy gauge); VLBM_ADJ_MULTIPASS=1 selects the multi-pass form
+        const char* mp = getenv("VLBM_ADJ_MULTIPASS");
+        ctx->adj_march = adjoint_march_supported(p) && !(mp && atoi(mp) != 0);
     }
     if (!ok) {
         vlbm_destroy(ctx);
@@ -304,7 +311,7 @@ void vlbm_destroy(vlbm_ctx* ctx)
     for (void* p : {ctx->f[0], ctx->f[1], (void*)ctx->ring, (void*)ctx->stop_at, (void*)ctx->err,
                     (void*)ctx->raw_err, (void*)ctx->scratchW, (void*)ctx->scratchB, (void*)ctx->partials,
                     (void*)ctx->norms_scratch, ctx->adj.aux, (void*)ctx->adj.partials, (void*)ctx->adj.qmax,
-                    (void*)ctx->adj.argmax})
+                    (void*)ctx->adj.argmax, (void*)ctx->adj.rec})
         if (p) (void)hipFree(p);
     if (ctx->host) (void)hipHostFree(ctx->host);
     if (ctx->host_u) (void)hipHostFree(ctx->host_u);
@@ -560,7 +567,10 @@ vlbm_status vlbm_raw_adjoint_step(vlbm_ctx* ctx, const void* f_n, const double* 
     if (vlbm_status st = need_unshifted(ctx)) return st;
     if (!f_n || !norms_n || !lam_np1 || !lam_n) return fail(ctx, VLBM_EINVAL, "null argument");
     if (lam_np1 == lam_n) return fail(ctx, VLBM_EINVAL, "lam_np1 and lam_n must differ");
-    HIPCHK(ctx, launch_adjoint_step(ctx->kp, ctx->prec, f_n, norms_n, lam_np1, lam_n, ctx->adj, ctx->stream));
+    if (ctx->adj_march)
+        HIPCHK(ctx, launch_adjoint_march(ctx->kp, ctx->prec, f_n, norms_n, lam_np1, lam_n, ctx->adj.rec, ctx->stream));
+    else
+        HIPCHK(ctx, launch_adjoint_step(ctx->kp, ctx->prec, f_n, norms_n, lam_np1, lam_n, ctx->adj, ctx->stream));
     return VLBM_OK;
 }
 

@@ -34,11 +34,19 @@ struct AdjScratch {
     double* partials;            // per-block partial sums of the normaliser adjoint (4 per block)
     double* qmax;                // grid maxima of |Q_alpha,k| (4)
     unsigned long long* argmax;  // first maximiser of each |Q_alpha,k| (4)
+    double* rec;                 // fused D2Q4 adjoint: per-wavefront records (adjoint_march_records x 12)
 };
 size_t adjoint_partials_count(const KParams& p);
 size_t adjoint_aux_elems(const KParams& p);
 hipError_t launch_adjoint_step(const KParams& p, int prec, const void* f_n, const double* norms_n,
                                const void* lam_np1, void* lam_n, const AdjScratch& sc, hipStream_t st);
+// fused single-march adjoint of a D2Q4 step (vlbm_adjoint_march.hip): the same
+// map as launch_adjoint_step, in one pass over f, lam_np1 and lam_n plus a
+// one-workgroup fix-up of the normaliser term
+int adjoint_march_records(const KParams& p);
+bool adjoint_march_supported(const KParams& p);
+hipError_t launch_adjoint_march(const KParams& p, int prec, const void* f_n, const double* norms_n,
+                                const void* lam_np1, void* lam_n, double* rec, hipStream_t st);
 hipError_t launch_init_adjoint(const KParams& p, int prec, const double* W0, long long ncell, const void* lam0,
                                double* W0bar, hipStream_t st);
 

@@ -29,56 +29,10 @@
 // Every population is read once from HBM and written once; halo rows and
 // columns are re-read through L2.  S is the storage type of the populations,
 // C the arithmetic type.
-#include "vlbm_common.hpp"
+#include "vlbm_planes.hpp"
 
 namespace vlbm {
 
-template <typename T>
-__device__ __forceinline__ T shfl(T v, int src)
-{
-    return __shfl(v, src, 64);
-}
-
-// Buffer addressing of the population arrays: one resource per group of four
-// planes (base in SGPRs), the plane offset within the group in the scalar
-// offset and the cell's byte offset as the only per-lane operand, so that no
-// per-lane 64-bit address arithmetic is spent on the 32 loads and stores of a row.
-struct Planes {
-    __amdgpu_buffer_rsrc_t rs[4];
-    unsigned plane_bytes;
-};
-
-template <typename S>
-__device__ __forceinline__ Planes make_planes(const S* base, unsigned plane)
-{
-    Planes p;
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-        p.rs[g] = __builtin_amdgcn_make_buffer_rsrc((void*)(base + (size_t)4 * g * plane), (short)0, (int)0xffffffff,
-                                                    0x00020000);
-    p.plane_bytes = plane * (unsigned)sizeof(S);
-    return p;
-}
-
-__device__ __forceinline__ double bload(const Planes& p, int j, unsigned off, double)
-{
-    typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(p.rs[j >> 2], off, (j & 3) * p.plane_bytes, 0);
-    return __builtin_bit_cast(double, v);
-}
-__device__ __forceinline__ float bload(const Planes& p, int j, unsigned off, float)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.rs[j >> 2], off, (j & 3) * p.plane_bytes, 0));
-}
-__device__ __forceinline__ void bstore(const Planes& p, int j, unsigned off, double v)
-{
-    typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), p.rs[j >> 2], off, (j & 3) * p.plane_bytes, 0);
-}
-__device__ __forceinline__ void bstore(const Planes& p, int j, unsigned off, float v)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), p.rs[j >> 2], off, (j & 3) * p.plane_bytes, 0);
-}
 
 template <typename S, typename C, int EOS, int SENSOR>
 struct March {
@@ -102,7 +56,8 @@ struct March {
     C yprev[4], wpend[4];      // f*_{+y} of the last collided row, pending moments of the row below
     S pre[16];                 // populations of the next row to enter the march (loads in flight)
     // reductions of the new state: maxima, and the admissibility witnesses
-    C red_s, red_M[4], min_rho, min_cs2, min_gap, nan_acc;
+    C red_s, red_M[4];
+    int ebits;                 // admissibility of the new state: ERR_NONHYP | ERR_NONFINITE
 
     __device__ __forceinline__ void reduce(const C* w)
     {
@@ -111,10 +66,7 @@ struct March {
         const C ee = w[3] * irho - (C)0.5 * (vx * vx + vy * vy) + eoff;
         const C PP = eos_pressure<C, EOS>(g, w[0], ee);
         const C cs2 = eos_cs2<C, EOS>(g, w[0], ee);
-        min_rho = fmin(min_rho, w[0]);
-        min_cs2 = fmin(min_cs2, cs2);
-        if constexpr (EOS == 1) min_gap = fmin(min_gap, (C)1 - g.b * w[0]);
-        nan_acc += (cs2 + PP) * (C)0;   // NaN or Inf anywhere makes this NaN
+        ebits |= eos_check<C, EOS>(g, w[0], ee, cs2);
         red_s = fmax(red_s, fmax(fabs(vx), fabs(vy)) + fast_sqrt(cs2));
         const C h = fma(eoff, w[0], w[3]) + PP;   // physical rho E + P
         red_M[0] = fmax(red_M[0], fmax(fabs(w[1]), fabs(w[2])));
@@ -381,8 +333,7 @@ __global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep S
 #pragma unroll
     for (int k = 0; k < 4; ++k) m.yprev[k] = m.wpend[k] = m.red_M[k] = (C)0;
     m.red_s = (C)0;
-    m.min_rho = m.min_cs2 = m.min_gap = (C)1;
-    m.nan_acc = (C)0;
+    m.ebits = 0;
 
     if (m.Rb <= m.Re) m.load_row(m.Rb, m.pre);
     const int Rlast = m.y1 + 3;
@@ -396,8 +347,8 @@ __global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep S
 #pragma unroll
         for (int k = 0; k < 4; ++k) M[k] = (double)m.red_M[k];
         int bits = 0;
-        if (!(m.min_rho > (C)0) || !(m.min_cs2 > (C)0) || !(m.min_gap > (C)0)) bits |= ERR_NONHYP;
-        if (!isfinite(m.nan_acc) || !isfinite(m.red_s)) bits |= ERR_NONFINITE;
+        bits |= m.ebits;
+        if (!isfinite(m.red_s)) bits |= ERR_NONFINITE;
         wave_publish(St, (double)m.red_s, M, 4, bits);
     }
 }

@@ -193,16 +193,18 @@ RIEMANN_CONFIGS = {
 
 
 def riemann2d(n, config=3):
-    """Four-quadrant problem on [0, 1]^2, discontinuities along x = y = 1/2."""
+    """Four-quadrant problem on [0, 1]^2, discontinuities along x = y = 1/2.
+    With an odd n the centre row and column (x or y exactly 1/2) belong to the
+    east and north quadrants, so every cell is assigned."""
     x, dx = centres(n, 0.0, 1.0)
     X, Y = np.meshgrid(x, x)
     st = RIEMANN_CONFIGS[config]
-    rho = np.empty_like(X)
-    u = np.empty_like(X)
-    v = np.empty_like(X)
-    P = np.empty_like(X)
-    for q, mask in (("NE", (X > 0.5) & (Y > 0.5)), ("NW", (X < 0.5) & (Y > 0.5)),
-                    ("SW", (X < 0.5) & (Y < 0.5)), ("SE", (X > 0.5) & (Y < 0.5))):
+    rho = np.zeros_like(X)
+    u = np.zeros_like(X)
+    v = np.zeros_like(X)
+    P = np.zeros_like(X)
+    east, north = X >= 0.5, Y >= 0.5
+    for q, mask in (("NE", east & north), ("NW", ~east & north), ("SW", ~east & ~north), ("SE", east & ~north)):
         rho[mask], u[mask], v[mask], P[mask] = st[q]
     return conserved(IDEAL_AIR, rho, u, P, v), dx
 

@@ -188,3 +188,50 @@ def test_full_size_fp32_adjoint_sensor_b(precision):
     _say(precision, "Sensor B: rel L2 vs fp64 %.2e" % _rel(g, g64))
     assert _rel(g, g64) <= 0.1      # measured bound, regression guard
     assert _rel(g, g64) <= 1e-3     # the FP32 target
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 3e-4)])
+@pytest.mark.parametrize("shape,bc,sensor", [((131, 97), (1, 1, 1, 1), 2), ((131, 97), (0, 0, 1, 1), 2),
+                                             ((96, 160), (1, 1, 0, 0), 1), ((70, 70), (0, 0, 0, 0), 0)])
+def test_fused_and_multipass_adjoint_step(precision, tol, shape, bc, sensor, monkeypatch):
+    """One adjoint step on ragged grids spanning several strips and segments,
+    with every boundary mix: the single-march form and the multi-pass form
+    against the PyTorch FP64 vector-Jacobian product of the same step at the
+    same state (the GPU state, copied out).  FP32: rounding (6e-8) amplified by
+    the transposed sensor at the quadrant discontinuities; measured <= 7e-5."""
+    from oracle.torch_ref import step_vjp
+    from paper_2609_10639_amd import Solver
+    nx, ny = shape
+    n = max(nx, ny)
+    W0 = pr.riemann2d(n, 12)[0][:, :ny, :nx].copy()
+    W0 = W0 + 1e-3 * np.abs(W0).max(axis=(1, 2), keepdims=True) * pr.gaussian(11, W0.size).reshape(W0.shape)
+    cfg = dict(dim=2, nx=nx, ny=ny, dx=1.0 / n, bc=bc, retarget_every=0, c_fixed=4.5, sensor=sensor,
+               **pr.SENSOR_2D, eps_theta=1e-12, beta_const=0.9, **pr.IDEAL_AIR.config())
+    ref, errs = None, []
+    for multipass in ("0", "1"):
+        monkeypatch.setenv("VLBM_ADJ_MULTIPASS", multipass)
+        s = Solver(precision=precision, **cfg)
+        W = torch.tensor(W0, device="cuda")
+        f, nrm = s.new_populations(), s.new_norms()
+        s.raw_init(W, f, nrm)
+        f1, n1 = s.new_populations(), s.new_norms()
+        s.raw_step(f, nrm, f1, n1)      # a state with structure
+        lam = s.new_populations()
+        lam.copy_(torch.tensor(pr.gaussian(12, lam.numel()).reshape(lam.shape), dtype=lam.dtype))
+        out = s.new_populations()
+        out.zero_()
+        s.raw_adjoint_step(f1, n1, lam, out)
+        torch.cuda.synchronize()
+        shp = (4, 4, ny, nx)
+        fs = f1[:, :nx * ny].double().cpu().numpy().reshape(shp)
+        ls = lam[:, :nx * ny].double().cpu().numpy().reshape(shp)
+        g = out[:, :nx * ny].double().cpu().numpy().reshape(shp)
+        if ref is None:
+            ref = step_vjp(cfg, fs, ls)
+        d = np.abs(g - ref).max() / np.abs(ref).max()
+        _say("adjoint step", "multi-pass" if multipass == "1" else "fused", precision, shape, bc, sensor,
+             "nan cells %d" % int(np.isnan(g).sum()), "rel Linf vs reference %.2e" % d)
+        s.close()
+        errs.append((np.isfinite(g).all(), d))
+    for finite, d in errs:
+        assert finite and d <= tol

@@ -54,3 +54,11 @@ def test_bzt_states_match_paper_quadrants():
     assert abs(pr.BZT_LEFT[2] - 0.41396 / P_c) < 1e-6
     assert abs(pr.BZT_RIGHT[0] - 0.65 / rho_c) < 1e-12
     assert abs(pr.BZT_RIGHT[2] - 0.36763 / P_c) < 1e-6
+
+
+def test_riemann_quadrants_cover_odd_grids():
+    """Every cell is assigned a quadrant state, also on odd grids where the
+    centre lines fall on x = 1/2 and y = 1/2."""
+    for n in (7, 8, 131):
+        W, _ = pr.riemann2d(n, 12)
+        assert np.isfinite(W).all() and (W[0] > 0).all()
