@@ -99,9 +99,9 @@ int choose_seg_h(const KParams& p, int prec)
             cus = prop.multiProcessorCount;
     }
     int per_cu = step_d2q4_blocks_per_cu(p, prec);
-    if (per_cu <= 0) per_cu = 8;
-    const long long resident = (long long)cus * per_cu;
-    long long nsegs = std::max(1LL, resident / p.nstrips);
+    if (per_cu <= 0) per_cu = 8 / p.wpg > 0 ? 8 / p.wpg : 1;
+    const long long resident = (long long)cus * per_cu;   // workgroups resident at once
+    long long nsegs = std::max(1LL, resident / p.ngroups);
     int h = (int)((p.ny + nsegs - 1) / nsegs);
     h = std::max(h, 16);
     return std::min(h, p.ny);
@@ -259,6 +259,17 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
         if (v >= 8 && v <= 58 && v % 2 == 0) p.strip_w = v;
     }
     p.nstrips = (p.nx + p.strip_w - 1) / p.strip_w;
+    // adjacent strips per workgroup (measured on MI355X): 2 FP64 wavefronts
+    // (24 KB of LDS ring each); with FP32 storage 4 on large grids, where the
+    // shared halo lines save HBM traffic, and 1 below 4M cells, where the march
+    // is latency-bound and the per-row barrier costs more than it saves
+    p.wpg = ctx->prec == PREC_FP64 ? 2 : (p.nx * (long long)p.ny >= (1LL << 22) ? 4 : 1);
+    if (const char* env = getenv("VLBM_WPG")) {
+        const int v = atoi(env);
+        if (v >= 1 && v <= 4) p.wpg = v;
+    }
+    p.wpg = std::min(p.wpg, p.nstrips);
+    p.ngroups = (p.nstrips + p.wpg - 1) / p.wpg;
     p.seg_h = p.ny;
     p.nsegs = 1;
     if (cfg->dim == 2) {

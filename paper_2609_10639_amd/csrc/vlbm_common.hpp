@@ -22,6 +22,7 @@ struct KParams {
     double beta_const, beta_min, beta_max, c_sensor, eps_theta;
     int strip_w;              // D2Q4: output columns per wavefront (a whole number of 128-byte lines)
     int nstrips, seg_h, nsegs; // D2Q4 tiling: strips of columns x segments of rows
+    int wpg, ngroups;         // D2Q4 step: wavefronts (adjacent strips) per workgroup, strip groups
 };
 
 // Per-launch control: where the clock and the reductions of the current state

@@ -273,11 +273,19 @@ struct March {
     }
 };
 
+// Dynamic LDS: one 3-row ring of raw populations per wavefront.
+extern __shared__ __align__(16) unsigned char vlbm_step_lds[];
+
+// A workgroup holds P.wpg wavefronts on adjacent strips of the same segment.
+// They march in step (one barrier per row), so the halo lines that
+// neighbouring strips both read are fetched from HBM once and served to the
+// second reader from the caches.
 template <typename S, typename C, int EOS, int SENSOR>
-__global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep St, const S* __restrict__ fin,
-                                                  S* __restrict__ fout)
+__global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep St, const S* __restrict__ fin,
+                                                   S* __restrict__ fout)
 {
-    __shared__ S ring[3][16][64];
+    const int wave = threadIdx.x >> 6;
+    S (*ring)[16][64] = reinterpret_cast<S (*)[16][64]>(vlbm_step_lds) + 3 * wave;
 
     double c_old, c_new, t, dt;
     bool last;
@@ -302,9 +310,10 @@ __global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep S
     m.eoff = (C)P.e_off;
     m.nx = P.nx;
     m.ny = P.ny;
-    m.lane = threadIdx.x;
+    m.lane = threadIdx.x & 63;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int strip = tile % P.nstrips, seg = tile / P.nstrips;
+    const int group = tile % P.ngroups, seg = tile / P.ngroups;
+    const int strip = group * P.wpg + wave;   // past the last strip: a wavefront that owns nothing
     const int halo = (64 - P.strip_w) / 2;
     m.X = strip * P.strip_w - halo + m.lane;
     int cx = m.X;
@@ -317,7 +326,7 @@ __global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep S
     if (P.bc[1] == 1 && m.X == m.nx - 1) m.rnb = m.lane;
     m.lnb = max(m.lnb, 0);
     m.rnb = min(m.rnb, 63);
-    m.owner = m.lane >= halo && m.lane < halo + P.strip_w && m.X < m.nx;
+    m.owner = m.lane >= halo && m.lane < halo + P.strip_w && m.X < m.nx && strip < P.nstrips;
     m.clo = P.bc[2] == 1;
     m.chi = P.bc[3] == 1;
     m.y0 = seg * P.seg_h;
@@ -337,10 +346,19 @@ __global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep S
 
     if (m.Rb <= m.Re) m.load_row(m.Rb, m.pre);
     const int Rlast = m.y1 + 3;
+    // every wavefront of the workgroup runs the same rows (same segment), so the
+    // barriers are reached uniformly
     for (int R = m.Rb; R <= Rlast; R += 3) {
         m.template iter<0>(R);
-        if (R + 1 <= Rlast) m.template iter<1>(R + 1);
-        if (R + 2 <= Rlast) m.template iter<2>(R + 2);
+        __syncthreads();
+        if (R + 1 <= Rlast) {
+            m.template iter<1>(R + 1);
+            __syncthreads();
+        }
+        if (R + 2 <= Rlast) {
+            m.template iter<2>(R + 2);
+            __syncthreads();
+        }
     }
     if (!St.probe) {
         double M[4];
@@ -358,13 +376,14 @@ __global__ void __launch_bounds__(64) k_step_d2q4(const KParams P, const KStep S
 template <typename S, typename C>
 static hipError_t launch_t(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
 {
-    const dim3 grid(p.nstrips * p.nsegs), block(64);
+    const dim3 grid(p.ngroups * p.nsegs), block(64 * p.wpg);
+    const size_t lds = (size_t)p.wpg * 3 * 16 * 64 * sizeof(S);
     const S* in = (const S*)fin;
     S* out = (S*)fout;
-#define VLBM_CASE(E, SN)                                                                     \
-    if (p.eos == E && p.sensor == SN) {                                                      \
-        hipLaunchKernelGGL((k_step_d2q4<S, C, E, SN>), grid, block, 0, st, p, s, in, out); \
-        return hipGetLastError();                                                            \
+#define VLBM_CASE(E, SN)                                                                       \
+    if (p.eos == E && p.sensor == SN) {                                                        \
+        hipLaunchKernelGGL((k_step_d2q4<S, C, E, SN>), grid, block, lds, st, p, s, in, out); \
+        return hipGetLastError();                                                              \
     }
     VLBM_CASE(0, 0) VLBM_CASE(0, 1) VLBM_CASE(0, 2) VLBM_CASE(1, 0) VLBM_CASE(1, 1) VLBM_CASE(1, 2)
 #undef VLBM_CASE
@@ -385,10 +404,12 @@ int step_d2q4_blocks_per_cu(const KParams& p, int prec)
 {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
+    const int bs = 64 * p.wpg;
+    const size_t l8 = (size_t)p.wpg * 3 * 16 * 64 * 8, l4 = l8 / 2;
     switch (prec) {
-    case PREC_FP64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, double, 0, 2>, 64, 0); break;
-    case PREC_FP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, float, 0, 2>, 64, 0); break;
-    case PREC_FP32_MIXED: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, double, 0, 2>, 64, 0); break;
+    case PREC_FP64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, double, 0, 2>, bs, l8); break;
+    case PREC_FP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, float, 0, 2>, bs, l4); break;
+    case PREC_FP32_MIXED: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, double, 0, 2>, bs, l4); break;
     }
     return e == hipSuccess ? nb : 0;
 }
