@@ -128,3 +128,12 @@ def primitives(W, gamma=1.4):
     ke = sum(0.5 * v * v for v in vel)
     P = (gamma - 1.0) * (W[D + 1] - rho * ke)
     return (rho, *vel, P)
+
+
+def gresho_speed(n):
+    """|u| of the steady Gresho vortex (Sec. IV.A) at the centres of an n x n
+    grid on [0, 1]^2: 5r for r < 0.2, 2 - 5r for 0.2 <= r < 0.4, 0 beyond."""
+    import numpy as np
+    c = (np.arange(n) + 0.5) / n - 0.5
+    r = np.sqrt(c[None, :] ** 2 + c[:, None] ** 2)
+    return np.where(r < 0.2, 5.0 * r, np.where(r < 0.4, 2.0 - 5.0 * r, 0.0))

@@ -83,6 +83,7 @@ class Gas:
 
 
 IDEAL_AIR = Gas(IDEAL, 1.4)
+IDEAL_MONO = Gas(IDEAL, 5.0 / 3.0)
 # reduced van der Waals units rho_c = P_c = 1 (a = 3, b = 1/3, R = 1), c_v/R = 50
 VDW_REDUCED_CV50 = Gas(VDW, 1.0 + 1.0 / 50.0, 3.0, 1.0 / 3.0, 1.0)
 
@@ -181,6 +182,25 @@ def vortex_perturbed(n, amplitude=1e-3, seed=42, L=10.0, strength=5.0):
     W, dx = vortex(n, L, strength)
     xi = gaussian(seed, W.size).reshape(W.shape)
     return W + amplitude * xi, dx
+
+
+def gresho(n, P0=5.0):
+    """Gresho vortex on the periodic [0, 1]^2 (Sec. IV.A): rho = 1, gamma = 5/3,
+    azimuthal speed 5r (r < 0.2), 2 - 5r (0.2 <= r < 0.4), 0 beyond, about the
+    centre (1/2, 1/2), with the pressure that balances it; a steady solution."""
+    x, dx = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x)
+    ox, oy = X - 0.5, Y - 0.5
+    r = np.hypot(ox, oy)
+    uphi = np.where(r < 0.2, 5.0 * r, np.where(r < 0.4, 2.0 - 5.0 * r, 0.0))
+    rs = np.maximum(r, 1e-300)
+    P = np.where(r < 0.2, P0 + 12.5 * r * r,
+                 np.where(r < 0.4, P0 + 12.5 * r * r + 4.0 * (1.0 - 5.0 * r - math.log(0.2) + np.log(rs)),
+                          P0 - 2.0 + 4.0 * math.log(2.0)))
+    # (u, v) = u_phi (-sin phi, cos phi) with sin phi = oy/r, cos phi = ox/r
+    u = np.where(r > 0, -uphi * oy / rs, 0.0)
+    v = np.where(r > 0, uphi * ox / rs, 0.0)
+    return conserved(IDEAL_MONO, np.ones_like(X), u, P, v), dx
 
 
 # Four-quadrant states (rho, u, v, P) of the paper's 2-D Riemann problems.

@@ -43,6 +43,26 @@ def energy_gauge(W0):
     return float(np.mean((W0[D + 1] - ke) / rho))
 
 
+def gresho_case(n=100, sensor="B"):
+    """Gresho vortex to t = 0.5 (Sec. IV.A): Sensor B with beta_min equal to the
+    stable constant beta 0.995 (the paper's rule for beta_min), or that
+    constant beta alone."""
+    W0, dx = pr.gresho(n)
+    cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, eps_theta=1e-12, **pr.IDEAL_MONO.config())
+    if sensor == "B":
+        cfg.update(sensor=2, beta_min=0.995, beta_max=1.0, c_sensor=16.0)
+    else:
+        cfg.update(sensor=0, beta_const=0.995)
+    return W0, cfg, 0.5
+
+
+def speed_error(W, n):
+    """L2 (root mean square) error of |u| against the steady Gresho solution."""
+    from oracle.exact import gresho_speed
+    sp = np.hypot(W[1] / W[0], W[2] / W[0])
+    return float(np.sqrt(np.mean((sp - gresho_speed(n)) ** 2)))
+
+
 def oracle_for(cfg, W0):
     kw = {k: v for k, v in cfg.items() if k not in ("precision", "e_offset")}
     o = core.Oracle(**kw)

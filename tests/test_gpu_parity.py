@@ -18,8 +18,8 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import (bzt1d_case, bzt2d_case, energy_gauge, oracle_for, rel_errors, riemann_case, sod_case,
-                     vortex_case)
+from helpers import (bzt1d_case, bzt2d_case, energy_gauge, gresho_case, oracle_for, rel_errors, riemann_case,
+                     sod_case, speed_error, vortex_case)
 
 pytestmark = pytest.mark.gpu
 
@@ -237,6 +237,50 @@ def test_energy_gauge_rejected_by_adjoint():
     lam = s.new_populations()
     with pytest.raises(N.VlbmError):
         s.raw_adjoint_step(f, n, lam, s.new_populations())
+
+
+# ------------------------------------------------------------------ Gresho vortex
+
+
+@pytest.mark.parametrize("precision,tol", [
+    ("fp64", 1e-11), ("fp32_mixed", 1e-5),
+    pytest.param("fp32", 1e-5, marks=pytest.mark.xfail(
+        strict=False, reason="FP32 arithmetic on a pressure-dominated momentum flux (P ~ 5, |u| <= 1): momentum "
+                             "relative Linf 1.8e-5 after 571 steps; FP32 storage with FP64 arithmetic meets 1e-5"))])
+def test_gresho_against_oracle(precision, tol):
+    """Gresho vortex (Sec. IV.A), 128^2 to t = 0.5 with Sensor B: parity with the
+    oracle (relative Linf per field)."""
+    W0, cfg, t_end = gresho_case(128, "B")
+    o, n_o, s, n_g = _run_both(W0, cfg, t_end, precision)
+    assert s.clock()[0] == t_end
+    errs = rel_errors(s.W(), o.W())
+    _say(precision, "gresho", n_g, n_o, ["%.2e/%.2e" % e for e in errs])
+    if precision == "fp64":
+        assert n_g == n_o
+    for e in errs:
+        assert e[0] <= tol
+
+
+def test_gresho_convergence():
+    """|u| error against the exact steady state at N = 100, 200, 400 (the paper's
+    grids): Sensor B against the stable constant beta = 0.995.  The sensor is
+    below the constant-beta error at every N and its error keeps falling faster
+    than first order on average over the three grids."""
+    from paper_2609_10639_amd import Solver
+    err = {}
+    for sensor in ("B", "const"):
+        for n in (100, 200, 400):
+            W0, cfg, t_end = gresho_case(n, sensor)
+            s = Solver(**cfg)
+            s.init(W0)
+            s.run_to_time(t_end)
+            err[sensor, n] = speed_error(s.W(), n)
+    _say("gresho L2(|u|):", {k: "%.3e" % v for k, v in err.items()})
+    for n in (100, 200, 400):
+        assert err["B", n] < err["const", n]
+    order = math.log2(err["B", 100] / err["B", 400]) / 2.0
+    _say("Sensor B observed order 100->400: %.2f" % order)
+    assert order >= 1.1
 
 
 # ------------------------------------------------------------------ invariants
