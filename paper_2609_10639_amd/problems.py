@@ -130,6 +130,42 @@ def sod(n=1000):
     return shock_tube(n, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
 
 
+def strong_shock_tube(n=2000):
+    """Strong shock tube (Sec. IV.C): (1, 0, 1000) | (1, 0, 0.01), ideal
+    gamma = 1.4, [0, 1], discontinuity at x = 1/2."""
+    return shock_tube(n, (1.0, 0.0, 1000.0), (1.0, 0.0, 0.01))
+
+
+# Argrow van der Waals shock tubes (Sec. IV.D): reduced units a = 3, b = 1/3,
+# R = 1; per case R/c_v, left and right (rho, u, P) and the end time.
+ARGROW_CASES = {
+    "I": dict(R_over_cv=0.0125, left=(0.879, 0.0, 1.09), right=(0.562, 0.0, 0.885), t_end=0.45),
+    "II": dict(R_over_cv=0.329, left=(1.01, 0.0, 1.6077), right=(0.594, 0.0, 0.8957), t_end=0.20),
+    "III": dict(R_over_cv=0.0125, left=(1.818, 0.0, 3.00), right=(0.275, 0.0, 0.575), t_end=0.15),
+}
+
+
+def argrow_gas(case):
+    """van der Waals gas of an Argrow case: gamma = 1 + R/c_v."""
+    return Gas(VDW, 1.0 + ARGROW_CASES[case]["R_over_cv"], 3.0, 1.0 / 3.0, 1.0)
+
+
+def argrow_tube(n, case):
+    c = ARGROW_CASES[case]
+    return shock_tube(n, c["left"], c["right"], gas=argrow_gas(case))
+
+
+def shu_osher(n=5000):
+    """Shu-Osher problem (Sec. IV.B) on [-5, 5]: (3.857143, 2.629369, 10.33333)
+    for x < -4, else (1 + 0.2 sin 5x, 0, 1); ideal gamma = 1.4."""
+    x, dx = centres(n, -5.0, 5.0)
+    L = x < -4.0
+    rho = np.where(L, 3.857143, 1.0 + 0.2 * np.sin(5.0 * x))
+    u = np.where(L, 2.629369, 0.0)
+    P = np.where(L, 10.33333, 1.0)
+    return conserved(IDEAL_AIR, rho, u, P).reshape(3, 1, n), dx
+
+
 # BZT tube states in reduced vdW units (c_v/R = 50): the paper's south-east and
 # north-east quadrant states of its BZT Riemann problem (Eq. 49, a = 1, b = 0.3),
 # converted by rho/rho_c, P/P_c, u/sqrt(P_c/rho_c) with rho_c = 1/(3b),

@@ -1,7 +1,7 @@
 """Shared test helpers: run the oracle and the GPU library on the same inputs."""
 import numpy as np
 
-from oracle import core
+from oracle import core, muscl
 from paper_2609_10639_amd import problems as pr
 
 # workloads: (builder, config) pairs with the paper's boundary and sensor choices
@@ -83,3 +83,50 @@ def rel_errors(a, b):
         ref = np.sqrt((y ** 2).sum(axis=0))
         out.append((d.max() / max(ref.max(), 1e-300), d.sum() / max(ref.sum(), 1e-300)))
     return out
+
+
+# ------------------------------------------- the paper's 1-D shock tubes
+
+
+def tube_primitives(W, gas):
+    """(rho, u, P) of a 1-D state under the gas's EOS, written out here."""
+    rho = W[0, 0]
+    u = W[1, 0] / rho
+    e = W[2, 0] / rho - 0.5 * u * u
+    if gas.eos == pr.IDEAL:
+        P = (gas.gamma - 1.0) * rho * e
+    else:
+        T = (e + gas.a * rho) / gas.cv
+        P = gas.R * rho * T / (1.0 - gas.b * rho) - gas.a * rho * rho
+    return rho, u, P
+
+
+def _tube(case):
+    if case == "strong":
+        return pr.strong_shock_tube, pr.IDEAL_AIR, 0.012
+    return (lambda n: pr.argrow_tube(n, case)), pr.argrow_gas(case), pr.ARGROW_CASES[case]["t_end"]
+
+
+def tube_config(case, n):
+    """D1Q2 configuration of the paper's shock tubes: outflow ends, CFL 0.8,
+    Sensor A with (0.75, 1, 4) (Sec. IV.C, reused for Sec. IV.D)."""
+    build, gas, t_end = _tube(case)
+    W0, dx = build(n)
+    cfg = dict(dim=1, nx=n, ny=1, dx=dx, bc=(1, 1, 1, 1), cfl=0.8, sensor=1, eps_theta=1e-12,
+               **pr.SENSOR_1D, **gas.config())
+    return W0, cfg, t_end
+
+
+def reference_primitives(case, n, n_ref):
+    """MUSCL reference at n_ref cells, cell-averaged onto n cells."""
+    build, gas, t_end = _tube(case)
+    m = n_ref // n
+    W0, dx = build(n_ref)
+    W, _ = muscl.run(W0, 1, n_ref, 1, dx, (1, 1, 1, 1), t_end, **gas.config())
+    return tube_primitives(W.reshape(3, 1, n, m).mean(axis=3), gas)
+
+
+def l1_errors(case, W, n, n_ref):
+    _, gas, _ = _tube(case)
+    ref = reference_primitives(case, n, n_ref)
+    return dict(zip(("rho", "u", "P"), (float(np.mean(np.abs(a - b))) for a, b in zip(tube_primitives(W, gas), ref))))
