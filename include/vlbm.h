@@ -57,7 +57,13 @@ typedef enum {
     VLBM_ENONFINITE = -5       /* NaN or Inf in the state */
 } vlbm_status;
 
-enum { VLBM_BC_PERIODIC = 0, VLBM_BC_OUTFLOW = 1 };
+/* Boundary kinds.  OUTFLOW: edge-replicated ghost cell (every neighbour index is
+ * clamped into the grid).  PINNED (x edges only): the ghost cell holds a fixed
+ * conserved state W_b at equilibrium, so the populations streaming in across
+ * that edge are f^eq_i(W_b) at the current link speed (Eq. 20); the inflow edge
+ * of the shock-vortex problem (Sec. IV.H).  The sensor's stencils treat a pinned
+ * edge like an outflow edge. */
+enum { VLBM_BC_PERIODIC = 0, VLBM_BC_OUTFLOW = 1, VLBM_BC_PINNED = 2 };
 enum { VLBM_EOS_IDEAL = 0, VLBM_EOS_VDW = 1 };
 enum { VLBM_SENSOR_OFF = 0, VLBM_SENSOR_A = 1, VLBM_SENSOR_B = 2, VLBM_SENSOR_AUTO = 3 };
 /* precision of a context: FP64 populations and arithmetic; FP32 populations
@@ -71,7 +77,10 @@ typedef struct {
     int64_t nx, ny;          /* cells; ny == 1 when dim == 1; nx, ny >= 4 */
     double dx;               /* uniform spacing (dy == dx) */
     int32_t bc[4];           /* x-low, x-high, y-low, y-high: VLBM_BC_*; periodic must be set on both
-                                sides of an axis */
+                                sides of an axis; PINNED on x edges only */
+    double bc_state[2][4];   /* W_b = (rho, rho u[, rho v], rho E) held at the x-low ([0]) and x-high
+                                ([1]) edge when that edge is PINNED (physical energy gauge, first
+                                dim + 2 entries used); it must be admissible (EINVAL otherwise) */
     int32_t eos;             /* VLBM_EOS_IDEAL: P = (gamma-1) rho e (Eq. 15); VLBM_EOS_VDW (Eqs. 16-17) */
     double gamma;            /* heat-capacity ratio; for vdW gamma = 1 + R/c_v */
     double vdw_a, vdw_b, vdw_R;
@@ -156,7 +165,9 @@ size_t vlbm_population_bytes(const vlbm_ctx* ctx);
  * 16 doubles apart, of (s_max, then max_{x,alpha}|Q_alpha,k| for each component
  * k, Eq. 30); each quantity is the maximum over the copies (kernels spread
  * their atomic maxima over the copies).  The caller allocates it; raw_init and
- * raw_step overwrite their output array entirely.
+ * raw_step overwrite their output array entirely.  The adjoint entry points
+ * (raw_adjoint_step, raw_init_adjoint, raw_moments_adjoint) return EINVAL when
+ * e_offset != 0 or an edge is PINNED.
  * ------------------------------------------------------------------------- */
 #define VLBM_NORMS_LEN 256
 

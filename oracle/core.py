@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vlbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_vlbm.so")
 
-PERIODIC, OUTFLOW = 0, 1
+PERIODIC, OUTFLOW, PINNED = 0, 1, 2
 IDEAL, VDW = 0, 1
 SENSOR_OFF, SENSOR_A, SENSOR_B, SENSOR_AUTO = 0, 1, 2, 3
 OK, LANDED = 0, 1
@@ -26,6 +26,7 @@ class OrcConfig(ctypes.Structure):
         ("ny", ctypes.c_long),
         ("dx", ctypes.c_double),
         ("bc", ctypes.c_int * 4),
+        ("bc_state", (ctypes.c_double * 4) * 2),
         ("eos", ctypes.c_int),
         ("gamma", ctypes.c_double),
         ("vdw_a", ctypes.c_double),
@@ -108,6 +109,11 @@ def make_config(**kw):
         if k == "bc":
             for j in range(4):
                 cfg.bc[j] = int(v[j])
+        elif k == "bc_state":
+            # ((W_b at x-low), (W_b at x-high)): conserved states of pinned edges
+            for side in range(2):
+                for j, w in enumerate(v[side] if v[side] is not None else ()):
+                    cfg.bc_state[side][j] = float(w)
         else:
             setattr(cfg, k, v)
     return cfg

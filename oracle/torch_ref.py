@@ -36,6 +36,8 @@ class Frozen:
         if self.D == 1 and self.sensor == 2:
             self.sensor = 1
         ny, nx = cfg["ny"], cfg["nx"]
+        if any(b not in (0, 1) for b in cfg["bc"]):
+            raise ValueError("the frozen-speed reference step covers periodic and outflow edges only")
         self.idx_x = {d: self._nb(torch.arange(nx), d, nx, cfg["bc"][0], cfg["bc"][1]) for d in (-1, 1)}
         self.idx_y = {d: self._nb(torch.arange(ny), d, ny, cfg["bc"][2], cfg["bc"][3]) for d in (-1, 1)}
 

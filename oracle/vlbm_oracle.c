@@ -29,6 +29,10 @@
  *   - outflow = edge-replicated ghost cell: every neighbour index (streaming
  *     source, central differences, box filter) is clamped into the grid;
  *     periodic wraps.  s_max and M_k run over interior cells only;
+ *   - pinned x edge (the shock-vortex inflow of Sec. IV.H): the ghost cell
+ *     holds a fixed state W_b at equilibrium, so the populations that stream
+ *     in across that edge are f^eq_i(W_b) at the current link speed (Eq. 20);
+ *     the sensor's stencils treat the edge like an outflow edge;
  *   - with retarget_every = K > 1 a retarget is forced whenever s_max > c.
  *
  * Directions: i = 0 (+x), 1 (-x), 2 (+y), 3 (-y).  Components:
@@ -54,7 +58,8 @@ typedef struct {
     int dim;              /* 1 or 2 */
     long nx, ny;          /* ny == 1 when dim == 1 */
     double dx;            /* uniform spacing, dy == dx */
-    int bc[4];            /* xlo, xhi, ylo, yhi: 0 periodic, 1 outflow */
+    int bc[4];            /* xlo, xhi, ylo, yhi: 0 periodic, 1 outflow, 2 pinned (x edges only) */
+    double bc_state[2][4];/* conserved state W_b held at the x-low / x-high edge when pinned */
     int eos;              /* 0 ideal gas, 1 van der Waals */
     double gamma, vdw_a, vdw_b, vdw_R;
     double cfl;
@@ -74,6 +79,7 @@ typedef struct {
     double *s, *theta, *tmp, *sbar, *thetabar, *beta;
     double c, t;
     long n;
+    double pin_Q[2][2][4];          /* Euler flux Q_alpha,k of each pinned edge state */
 } orc_state;
 
 /* ------------------------------------------------------------------ EOS */
@@ -158,6 +164,31 @@ static int evec(int i, int a)
 #define UV(st, a, c) ((st)->u[(long)(a) * (st)->ncell + (c)])
 #define FLX(st, a, k, c) ((st)->flux[((long)(a) * (st)->NK + (k)) * (st)->ncell + (c)])
 
+/* Euler flux Q_alpha(W_b) (Eq. 10) of a pinned edge state, both axes; the
+ * state must be admissible. */
+static int pin_flux(const orc_config* g, const double* Wb, double Q[2][4])
+{
+    const int D = g->dim;
+    const double rho = Wb[0];
+    if (!(rho > 0.0)) return ORC_ENONHYP;
+    double u[2] = {0.0, 0.0}, ke = 0.0;
+    for (int a = 0; a < D; ++a) {
+        u[a] = Wb[1 + a] / rho;
+        ke += 0.5 * u[a] * u[a];
+    }
+    const double e = Wb[D + 1] / rho - ke;
+    const double P = eos_P(g, rho, e);
+    int st = eos_admissible(g, rho, e, eos_cs2(g, rho, e));
+    if (st != ORC_OK) return st;
+    if (!isfinite(P)) return ORC_ENONFINITE;
+    for (int a = 0; a < D; ++a) {
+        Q[a][0] = rho * u[a];
+        for (int b = 0; b < D; ++b) Q[a][1 + b] = rho * u[a] * u[b] + (a == b ? P : 0.0);
+        Q[a][D + 1] = (Wb[D + 1] + P) * u[a];
+    }
+    return ORC_OK;
+}
+
 /* ---------------------------------------------------------- lifecycle */
 
 int orc_create(const orc_config* cfg, orc_state** out)
@@ -166,9 +197,17 @@ int orc_create(const orc_config* cfg, orc_state** out)
     if (cfg->dim != 1 && cfg->dim != 2) return ORC_EINVAL;
     if (cfg->nx < 3 || (cfg->dim == 2 && cfg->ny < 3) || (cfg->dim == 1 && cfg->ny != 1)) return ORC_EINVAL;
     if (!(cfg->dx > 0)) return ORC_EINVAL;
+    for (int i = 0; i < 4; ++i)
+        if (cfg->bc[i] < 0 || cfg->bc[i] > (i < 2 ? 2 : 1)) return ORC_EINVAL;
+    double pin_Q[2][2][4] = {{{0}}};
+    for (int side = 0; side < 2; ++side) {
+        if (cfg->bc[side] != 2) continue;
+        if (pin_flux(cfg, cfg->bc_state[side], pin_Q[side]) != ORC_OK) return ORC_EINVAL;
+    }
     orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
     if (!s) return ORC_ENOMEM;
     s->cfg = *cfg;
+    memcpy(s->pin_Q, pin_Q, sizeof(pin_Q));
     s->D = cfg->dim;
     s->Q = 2 * cfg->dim;          /* Q = 2^D = 2D for D <= 2 (Sec. III.A) */
     s->NK = cfg->dim + 2;
@@ -426,15 +465,26 @@ static void sweep_collide(orc_state* s)
     }
 }
 
-/* Exact transport f_i(x, t + dt) = f*_i(x - dt c_i) (Eq. 21): a one-cell pull. */
+/* Exact transport f_i(x, t + dt) = f*_i(x - dt c_i) (Eq. 21): a one-cell pull.
+ * A source beyond a pinned x edge is that edge's ghost at equilibrium,
+ * f^eq_i(W_b) = W_b/(2D) + c_i . Q(W_b)/(2 c^2) (Eq. 20). */
 static void sweep_stream(orc_state* s)
 {
     const orc_config* g = &s->cfg;
+    const int D = s->D;
     for (int i = 0; i < s->Q; ++i)
         for (int k = 0; k < s->NK; ++k) {
 #pragma omp parallel for
             for (long c = 0; c < s->ncell; ++c) {
                 long x = c % g->nx, y = c / g->nx;
+                long xs = x - evec(i, 0);
+                int side = xs < 0 ? 0 : (xs >= g->nx ? 1 : -1);
+                if (side >= 0 && g->bc[side] == 2) {
+                    double cdotQ = 0.0;
+                    for (int a = 0; a < D; ++a) cdotQ += s->c * evec(i, a) * s->pin_Q[side][a][k];
+                    F(s, i, k, c) = g->bc_state[side][k] / (2.0 * D) + cdotQ / (2.0 * s->c * s->c);
+                    continue;
+                }
                 long src = nb_cell(s, x, y, -evec(i, 0), -evec(i, 1));
                 F(s, i, k, c) = FS(s, i, k, src);
             }

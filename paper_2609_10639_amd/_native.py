@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libvlbm.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONHYPERBOLIC, ENONFINITE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONHYPERBOLIC", -5: "ENONFINITE"}
-BC_PERIODIC, BC_OUTFLOW = 0, 1
+BC_PERIODIC, BC_OUTFLOW, BC_PINNED = 0, 1, 2
 EOS_IDEAL, EOS_VDW = 0, 1
 SENSOR_OFF, SENSOR_A, SENSOR_B, SENSOR_AUTO = 0, 1, 2, 3
 FP64, FP32, FP32_MIXED = 0, 1, 2
@@ -25,6 +25,7 @@ class VlbmConfig(ctypes.Structure):
         ("ny", ctypes.c_int64),
         ("dx", ctypes.c_double),
         ("bc", ctypes.c_int32 * 4),
+        ("bc_state", (ctypes.c_double * 4) * 2),
         ("eos", ctypes.c_int32),
         ("gamma", ctypes.c_double),
         ("vdw_a", ctypes.c_double),

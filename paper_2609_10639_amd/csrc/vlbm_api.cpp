@@ -174,8 +174,11 @@ bool check_config(const vlbm_config* c, std::string& why)
     if (c->dim == 2 && (c->ny < 4 || c->ny > (1LL << 30))) return why = "ny out of range", false;
     if (c->nx * c->ny > (1LL << 31)) return why = "grid too large", false;
     if (!(c->dx > 0) || !std::isfinite(c->dx)) return why = "dx must be positive", false;
-    for (int i = 0; i < 4; ++i)
-        if (c->bc[i] != VLBM_BC_PERIODIC && c->bc[i] != VLBM_BC_OUTFLOW) return why = "bad boundary kind", false;
+    for (int i = 0; i < 4; ++i) {
+        const bool pinned_ok = i < 2 && c->bc[i] == VLBM_BC_PINNED;
+        if (c->bc[i] != VLBM_BC_PERIODIC && c->bc[i] != VLBM_BC_OUTFLOW && !pinned_ok)
+            return why = "bad boundary kind (pinned is for x edges only)", false;
+    }
     if ((c->bc[0] == VLBM_BC_PERIODIC) != (c->bc[1] == VLBM_BC_PERIODIC))
         return why = "periodic x needs both x sides periodic", false;
     if (c->dim == 2 && (c->bc[2] == VLBM_BC_PERIODIC) != (c->bc[3] == VLBM_BC_PERIODIC))
@@ -185,6 +188,21 @@ bool check_config(const vlbm_config* c, std::string& why)
     if (c->eos == VLBM_EOS_VDW && (!(c->vdw_R > 0) || c->vdw_a < 0 || c->vdw_b < 0))
         return why = "bad van der Waals constants", false;
     if (!std::isfinite(c->e_offset)) return why = "e_offset must be finite", false;
+    for (int side = 0; side < 2; ++side) {
+        if (c->bc[side] != VLBM_BC_PINNED) continue;
+        const double* w = c->bc_state[side];
+        const int NK = c->dim + 2;
+        for (int k = 0; k < NK; ++k)
+            if (!std::isfinite(w[k])) return why = "pinned state must be finite", false;
+        if (!(w[0] > 0)) return why = "pinned state needs rho > 0", false;
+        double ke = 0.0;
+        for (int a = 0; a < c->dim; ++a) ke += 0.5 * w[1 + a] * w[1 + a] / w[0];
+        const double e = (w[NK - 1] - ke) / w[0];   // specific internal energy
+        // positive pressure (ideal) / temperature and co-volume (van der Waals, Eqs. 16-17)
+        if (c->eos == VLBM_EOS_IDEAL && !(e > 0)) return why = "pinned state needs e > 0", false;
+        if (c->eos == VLBM_EOS_VDW && (!(e + c->vdw_a * w[0] > 0) || !(c->vdw_b * w[0] < 1)))
+            return why = "pinned state needs T > 0 and b rho < 1", false;
+    }
     if (c->retarget_every < 0) return why = "retarget_every must be >= 0", false;
     if (c->retarget_every > 0 && !(c->cfl > 0 && c->cfl <= 1.0)) return why = "cfl must be in (0, 1]", false;
     if (c->retarget_every == 0 && !(c->c_fixed > 0)) return why = "c_fixed must be positive", false;
@@ -233,6 +251,8 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
     p.plane = ctx->plane;
     p.dx = cfg->dx;
     for (int i = 0; i < 4; ++i) p.bc[i] = cfg->bc[i];
+    for (int side = 0; side < 2; ++side)
+        for (int k = 0; k < 4; ++k) p.pin_w[side][k] = cfg->bc[side] == VLBM_BC_PINNED ? cfg->bc_state[side][k] : 0.0;
     p.eos = cfg->eos;
     p.gamma = cfg->gamma;
     p.vdw_a = cfg->vdw_a;
@@ -536,10 +556,13 @@ static vlbm_status need_frozen(vlbm_ctx* ctx)
     return VLBM_OK;
 }
 
-// the adjoint kernels work in the physical energy gauge
-static vlbm_status need_unshifted(vlbm_ctx* ctx)
+// the adjoint kernels work in the physical energy gauge, with periodic and
+// outflow edges
+static vlbm_status need_adjoint_support(vlbm_ctx* ctx)
 {
     if (ctx->cfg.e_offset != 0.0) return fail(ctx, VLBM_EINVAL, "the adjoint entry points need e_offset == 0");
+    if (ctx->cfg.bc[0] == VLBM_BC_PINNED || ctx->cfg.bc[1] == VLBM_BC_PINNED)
+        return fail(ctx, VLBM_EINVAL, "the adjoint entry points do not cover pinned edges");
     return VLBM_OK;
 }
 
@@ -575,7 +598,7 @@ vlbm_status vlbm_raw_adjoint_step(vlbm_ctx* ctx, const void* f_n, const double* 
                                   void* lam_n)
 {
     if (vlbm_status st = need_frozen(ctx)) return st;
-    if (vlbm_status st = need_unshifted(ctx)) return st;
+    if (vlbm_status st = need_adjoint_support(ctx)) return st;
     if (!f_n || !norms_n || !lam_np1 || !lam_n) return fail(ctx, VLBM_EINVAL, "null argument");
     if (lam_np1 == lam_n) return fail(ctx, VLBM_EINVAL, "lam_np1 and lam_n must differ");
     if (ctx->adj_march)
@@ -588,7 +611,7 @@ vlbm_status vlbm_raw_adjoint_step(vlbm_ctx* ctx, const void* f_n, const double* 
 vlbm_status vlbm_raw_init_adjoint(vlbm_ctx* ctx, const double* W0, const void* lam0, double* W0bar)
 {
     if (vlbm_status st = need_frozen(ctx)) return st;
-    if (vlbm_status st = need_unshifted(ctx)) return st;
+    if (vlbm_status st = need_adjoint_support(ctx)) return st;
     if (!W0 || !lam0 || !W0bar) return fail(ctx, VLBM_EINVAL, "null argument");
     HIPCHK(ctx, launch_init_adjoint(ctx->kp, ctx->prec, W0, ctx->ncell, lam0, W0bar, ctx->stream));
     return VLBM_OK;
@@ -604,7 +627,7 @@ vlbm_status vlbm_raw_moments(vlbm_ctx* ctx, const void* f, double* W)
 vlbm_status vlbm_raw_moments_adjoint(vlbm_ctx* ctx, const double* Wbar, void* lam)
 {
     if (!ctx || !Wbar || !lam) return fail(ctx, VLBM_EINVAL, "null argument");
-    if (vlbm_status st = need_unshifted(ctx)) return st;
+    if (vlbm_status st = need_adjoint_support(ctx)) return st;
     HIPCHK(ctx, launch_moments_adj(ctx->D, ctx->plane, ctx->ncell, ctx->fp32, Wbar, lam, ctx->stream));
     return VLBM_OK;
 }

@@ -12,7 +12,9 @@ struct KParams {
     int dim, nx, ny;
     long long plane;          // elements per population plane (padded)
     double dx;
-    int bc[4];                // x-lo, x-hi, y-lo, y-hi: 0 periodic, 1 outflow (clamped ghost)
+    int bc[4];                // x-lo, x-hi, y-lo, y-hi: 0 periodic, 1 outflow (clamped ghost),
+                              // 2 pinned (x edges: ghost at equilibrium of pin_w[side])
+    double pin_w[2][4];       // conserved state of a pinned x-lo / x-hi ghost (physical gauge)
     int eos;                  // 0 ideal, 1 van der Waals
     double gamma, vdw_a, vdw_b, vdw_R, inv_cv;
     double e_off;             // energy gauge: populations carry rho E - e_off rho in the energy component
@@ -158,6 +160,27 @@ __device__ __forceinline__ int eos_check(const Gas<T>& g, T rho, T e, T cs2)
 }
 
 // maximum over the copies of reduction field j of the current state
+// Population of direction +x (side 0: streams in across the x-low edge) or -x
+// (side 1: across the x-high edge) of a pinned ghost, the equilibrium of its
+// state W_b at the link speed of this step (Eq. 20): W_b/(2D) +- Q_x(W_b)/(2c),
+// returned in the stored energy gauge (energy rho E - eoff rho, flux Q_E - eoff Q_rho).
+template <typename T, int EOS>
+__device__ inline void pinned_feq(const KParams& p, const Gas<T>& g, int side, T inv2c, T eoff, T* out)
+{
+    const int D = p.dim, NK = D + 2;
+    const double* w = p.pin_w[side];
+    const T rho = (T)w[0], mx = (T)w[1], my = D == 2 ? (T)w[2] : (T)0, E = (T)w[NK - 1];
+    const T u = mx / rho, v = my / rho;
+    const T e = E / rho - (T)0.5 * (u * u + v * v);
+    const T P = eos_pressure<T, EOS>(g, rho, e);
+    const T sgn = side == 0 ? (T)1 : (T)-1;
+    const T inv2d = (T)1 / (T)(2 * D);
+    out[0] = rho * inv2d + sgn * mx * inv2c;
+    out[1] = mx * inv2d + sgn * (mx * u + P) * inv2c;
+    if (D == 2) out[2] = my * inv2d + sgn * (my * u) * inv2c;
+    out[NK - 1] = (E - eoff * rho) * inv2d + sgn * ((E + P) * u - eoff * mx) * inv2c;
+}
+
 __device__ __forceinline__ double red_fold(const KStep& s, int j)
 {
     double v = s.red_in[j];

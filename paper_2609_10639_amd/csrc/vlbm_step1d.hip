@@ -45,7 +45,10 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
     }
     const int nx = P.nx;
     const long long plane = P.plane;
-    const bool cl = P.bc[0] == 1, ch = P.bc[1] == 1;
+    // outflow and pinned edges clamp every neighbour index; a pinned edge then
+    // replaces the population streaming in across it by its ghost's equilibrium
+    const bool cl = P.bc[0] != 0, ch = P.bc[1] != 0;
+    const bool pl = P.bc[0] == 2, ph = P.bc[1] == 2;
     const int ntiles = (nx + kTile1 - 1) / kTile1;
 
     // reductions of the new state over every tile this block visits
@@ -142,6 +145,13 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
                 for (int k = 0; k < 3; ++k) {
                     gn[k] = sg[k][sl];
                     gn[3 + k] = sg[3 + k][sr];
+                }
+                if ((pl && X == 0) || (ph && X == nx - 1)) {   // nx >= 4: distinct cells
+                    T pe[3];
+                    const int side = X == 0 ? 0 : 1;
+                    pinned_feq<T, EOS>(P, g, side, inv2c, eoff, pe);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) gn[side * 3 + k] = pe[k];
                 }
 #pragma unroll
                 for (int j = 0; j < 6; ++j) fout[j * plane + X] = (ST)gn[j];

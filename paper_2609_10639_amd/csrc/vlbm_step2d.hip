@@ -34,6 +34,10 @@
 namespace vlbm {
 
 
+// +x equilibrium of a pinned x-low ghost, then -x of a pinned x-high ghost, at
+// this step's link speed (written once per workgroup before the march).
+__shared__ double vlbm_pin_lds[8];
+
 template <typename S, typename C, int EOS, int SENSOR>
 struct March {
     // uniform
@@ -153,6 +157,10 @@ struct March {
                     fyp[k] = am + cy;
                     fym[k] = am - cy;
                 }
+                // a pinned x edge: its ghost's equilibrium streams in instead (nx >= 4:
+                // X == 0 and X == nx - 1 are distinct columns).  Applied as a second
+                // store and in the pending moments, after the streaming stores.
+                const bool pin_lo = P.bc[0] == 2 && X == 0, pin_hi = P.bc[1] == 2 && X == nx - 1;
                 // streaming stores (pull semantics: a clamped ghost repeats the edge cell)
                 if (owner) {
                     const unsigned col = (unsigned)X * (unsigned)sizeof(S);
@@ -161,6 +169,12 @@ struct March {
                         const unsigned b = (unsigned)p * rowb + col;
 #pragma unroll
                         for (int j = 0; j < 8; ++j) bstore(out, j, b, (S)gx[j]);
+                        if (pin_lo)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) bstore(out, k, b, (S)(C)vlbm_pin_lds[k]);
+                        if (pin_hi)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) bstore(out, 4 + k, b, (S)(C)vlbm_pin_lds[4 + k]);
                         if (plo)
 #pragma unroll
                             for (int k = 0; k < 4; ++k) bstore(out, 8 + k, b, (S)fyp[k]);
@@ -191,7 +205,9 @@ struct March {
                     for (int k = 0; k < 4; ++k) yprev[k] = fyp[k];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    wpend[k] = (gx[k] + gx[4 + k]) + yprev[k];
+                    const C gl = pin_lo ? (C)vlbm_pin_lds[k] : gx[k];
+                    const C gr = pin_hi ? (C)vlbm_pin_lds[4 + k] : gx[4 + k];
+                    wpend[k] = (gl + gr) + yprev[k];
                     yprev[k] = fyp[k];
                 }
                 if (phi && owner && p >= y0 && p < y1) {
@@ -293,6 +309,16 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
     if (blockIdx.x == 0 && threadIdx.x == 0) write_clock(St, t, dt, c_new, last);
     if (blockIdx.x == 0 && threadIdx.x < 64 && !St.frozen) clear_reductions(St, threadIdx.x);
 
+    if (P.bc[0] == 2 || P.bc[1] == 2) {
+        if (threadIdx.x < 2 && P.bc[threadIdx.x] == 2) {
+            C pe[4];
+            pinned_feq<C, EOS>(P, make_gas<C>(P), (int)threadIdx.x, (C)(0.5 / c_new), (C)P.e_off, pe);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) vlbm_pin_lds[4 * threadIdx.x + k] = (double)pe[k];
+        }
+        __syncthreads();
+    }
+
     March<S, C, EOS, SENSOR> m{P, St};
     m.in = make_planes(fin, (unsigned)P.plane);
     m.out = make_planes((const S*)fout, (unsigned)P.plane);
@@ -322,8 +348,9 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
     m.colx = (unsigned)cx;
     m.lnb = m.lane - 1;
     m.rnb = m.lane + 1;
-    if (P.bc[0] == 1 && m.X == 0) m.lnb = m.lane;
-    if (P.bc[1] == 1 && m.X == m.nx - 1) m.rnb = m.lane;
+    if (P.bc[0] != 0 && m.X == 0) m.lnb = m.lane;   // outflow and pinned edges clamp the stencils
+    if (P.bc[1] != 0 && m.X == m.nx - 1) m.rnb = m.lane;
+
     m.lnb = max(m.lnb, 0);
     m.rnb = min(m.rnb, 63);
     m.owner = m.lane >= halo && m.lane < halo + P.strip_w && m.X < m.nx && strip < P.nstrips;

@@ -212,6 +212,28 @@ def vortex(n, L=10.0, strength=5.0, t=0.0):
     return conserved(IDEAL_AIR, rho, u, P, v), dx
 
 
+def vortex_in_stream(nx, ny, dx, speed=2.0, centre=None, strength=5.0):
+    """Isentropic vortex (the Yee/Shu profile above, rho = P = 1 far away) in a
+    uniform stream (speed, 0) on [0, nx dx] x [0, ny dx], periodic images in y
+    only.  Returns W and the free-stream state (1, speed, 0, 1) as conserved
+    variables: the state to hold at an upstream pinned edge."""
+    Lx, Ly = nx * dx, ny * dx
+    cx, cy = centre if centre is not None else (0.5 * Lx, 0.5 * Ly)
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dx
+    X, Y = np.meshgrid(x, y)
+    dxp = X - cx
+    dyp = (Y - cy + 0.5 * Ly) % Ly - 0.5 * Ly
+    r2 = dxp * dxp + dyp * dyp
+    g = IDEAL_AIR.gamma
+    amp = strength / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+    T = 1.0 - (g - 1.0) * strength ** 2 / (8.0 * g * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = T ** (1.0 / (g - 1.0))
+    W = conserved(IDEAL_AIR, rho, speed - amp * dyp, rho * T, amp * dxp)
+    W_inf = conserved(IDEAL_AIR, np.ones(1), np.full(1, speed), np.ones(1), np.zeros(1))[:, 0]
+    return W, W_inf
+
+
 def vortex_perturbed(n, amplitude=1e-3, seed=42, L=10.0, strength=5.0):
     """Vortex initial state plus amplitude * N(0, 1) on every component of W,
     independent per cell and component (seeded SplitMix64 + Box-Muller)."""

@@ -21,7 +21,8 @@ class Solver:
     """VLBM solver on the current GPU.
 
     Keyword arguments follow `vlbm_config` (include/vlbm.h): dim, nx, ny, dx,
-    bc (4-tuple), eos, gamma, vdw_a, vdw_b, vdw_R, e_offset, cfl, retarget_every,
+    bc (4-tuple; 0 periodic, 1 outflow, 2 pinned), bc_state (pair of conserved
+    states held at pinned x-low / x-high edges, None where unused), eos, gamma, vdw_a, vdw_b, vdw_R, e_offset, cfl, retarget_every,
     c_fixed, sensor, beta_const, beta_min, beta_max, c_sensor, eps_theta,
     precision ("fp64" | "fp32" | "fp32_mixed": FP32 populations with FP64 arithmetic).
     """
@@ -40,6 +41,10 @@ class Solver:
             if k == "bc":
                 for j in range(4):
                     cfg.bc[j] = int(v[j])
+            elif k == "bc_state":
+                for side in range(2):
+                    for j, w in enumerate(v[side] if v[side] is not None else ()):
+                        cfg.bc_state[side][j] = float(w)
             elif k == "precision":
                 cfg.precision = {"fp64": N.FP64, "fp32": N.FP32, "fp32_mixed": N.FP32_MIXED}.get(v, v)
             else:

@@ -41,9 +41,18 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
         _native.lib()
 
 
-def test_config_struct_matches_header_layout():
+def test_config_struct_matches_header_layout(tmp_path):
+    """Every field of the ctypes mirror sits at the offset the C compiler gives
+    it in include/vlbm.h (gcc prints offsetof for each field)."""
+    import subprocess
     from paper_2609_10639_amd import _native
-    # dim(4)+pad(4) nx ny dx bc[4] eos gamma a b R cfl retarget c_fixed sensor 5 doubles precision stream
-    c = _native.VlbmConfig
-    assert c.nx.offset == 8 and c.dx.offset == 24 and c.bc.offset == 32 and c.eos.offset == 48
-    assert c.gamma.offset == 56 and c.stream.offset == ctypes.sizeof(c) - 8
+    fields = [f for f, _ in _native.VlbmConfig._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"vlbm.h\"\nint main(void) {\n" +
+                   "".join('printf("%%zu\\n", offsetof(vlbm_config, %s));\n' % f for f in fields) +
+                   'printf("%zu\\n", sizeof(vlbm_config));\nreturn 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [getattr(_native.VlbmConfig, f).offset for f in fields] + [ctypes.sizeof(_native.VlbmConfig)]
+    assert got == want, list(zip(fields + ["sizeof"], got, want))

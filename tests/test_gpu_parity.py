@@ -372,7 +372,9 @@ def test_bad_configs_rejected():
     from paper_2609_10639_amd import _native as N
     W0, cfg, _ = sod_case(100)
     for bad in (dict(cfl=0.0), dict(bc=(0, 1, 1, 1)), dict(nx=2), dict(beta_min=1.2), dict(dim=3),
-                dict(retarget_every=0, c_fixed=0.0)):
+                dict(retarget_every=0, c_fixed=0.0), dict(bc=(2, 1, 1, 1), bc_state=((0.0, 0.0, 1.0), None)),
+                dict(bc=(2, 1, 1, 1), bc_state=((1.0, 0.0, -1.0), None)), dict(bc=(3, 1, 1, 1)),
+                dict(bc=(2, 0, 1, 1), bc_state=((1.0, 0.0, 2.5), None))):
         with pytest.raises(N.VlbmError):
             _solver(dict(cfg, **bad))
 
