@@ -11,7 +11,9 @@
  *     max(|u_n| + c_s) of the two states;
  *   * Heun's two-stage Runge-Kutta (strong-stability-preserving RK2);
  *   * dt = CFL dx / max(|u_a| + c_s), the last step shortened to land on t_end;
- *   * boundaries: outflow (two zero-gradient ghost cells) or periodic;
+ *   * boundaries: outflow (two zero-gradient ghost cells), periodic, or (x
+ *     edges) pinned: both ghost cells hold a fixed state W_b (the inflow edge
+ *     of the shock-vortex problem, Sec. IV.H);
  *   * 2-D by summing the x and y face fluxes of each stage.
  * EOS (Sec. II.C): ideal P = (gamma-1) rho e, or van der Waals
  * P = R rho T/(1 - b rho) - a rho^2 with e = c_v T - a rho, c_v = R/(gamma-1);
@@ -25,7 +27,8 @@
 typedef struct {
     int dim, nx, ny;
     double dx;
-    int bc[4];          /* x-low, x-high, y-low, y-high: 0 periodic, 1 outflow */
+    int bc[4];          /* x-low, x-high, y-low, y-high: 0 periodic, 1 outflow, 2 pinned (x only) */
+    double bc_state[2][4]; /* conserved W_b of a pinned x-low / x-high edge */
     int eos;            /* 0 ideal, 1 van der Waals */
     double gamma, a, b, R;
     double cfl;
@@ -117,6 +120,17 @@ static void to_primitives(const ms_config* c, const double* W, prim_t* p)
     for (int jj = 0; jj < p->py; ++jj)
         for (int ii = 0; ii < p->px; ++ii) {
             int i = ii - NG, j = jj - gy;
+            const int side = i < 0 ? 0 : (i >= nx ? 1 : -1);
+            if (side >= 0 && c->bc[side] == 2) {
+                const double* w = c->bc_state[side];
+                double ke = 0.0;
+                for (int b = 0; b < D; ++b) ke += 0.5 * w[1 + b] * w[1 + b] / (w[0] * w[0]);
+                double* q = p->q + (long long)jj * p->px + ii;
+                q[0] = w[0];
+                for (int b = 0; b < D; ++b) q[(1 + b) * pl] = w[1 + b] / w[0];
+                q[(D + 1) * pl] = pressure(c, w[0], w[D + 1] / w[0] - ke);
+                continue;
+            }
             if (i < 0) i = c->bc[0] == 0 ? wrap(i, nx) : 0;
             if (i >= nx) i = c->bc[1] == 0 ? wrap(i, nx) : nx - 1;
             if (D == 2) {

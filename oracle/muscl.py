@@ -18,7 +18,7 @@ _LIB = os.path.join(_HERE, "libmuscl_ref.so")
 
 class MsConfig(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("dx", ctypes.c_double),
-                ("bc", ctypes.c_int * 4), ("eos", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("bc", ctypes.c_int * 4), ("bc_state", (ctypes.c_double * 4) * 2), ("eos", ctypes.c_int), ("gamma", ctypes.c_double),
                 ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double), ("cfl", ctypes.c_double)]
 
 
@@ -50,11 +50,14 @@ def _get():
 
 
 def _config(dim=1, nx=1, ny=1, dx=1.0, bc=(1, 1, 1, 1), cfl=0.4, eos=0, gamma=1.4, vdw_a=0.0, vdw_b=0.0,
-            vdw_R=1.0):
+            vdw_R=1.0, bc_state=(None, None)):
     c = MsConfig()
     c.dim, c.nx, c.ny, c.dx = dim, nx, ny, dx
     for i in range(4):
         c.bc[i] = int(bc[i])
+    for side in range(2):
+        for j, w in enumerate(bc_state[side] if bc_state[side] is not None else ()):
+            c.bc_state[side][j] = float(w)
     c.eos, c.gamma, c.a, c.b, c.R, c.cfl = eos, gamma, vdw_a, vdw_b, vdw_R, cfl
     return c
 
@@ -67,10 +70,12 @@ def state(rho, P, eos=0, gamma=1.4, vdw_a=0.0, vdw_b=0.0, vdw_R=1.0, **_):
     return tuple(out)
 
 
-def run(W0, dim, nx, ny, dx, bc, t_end, cfl=0.4, eos=0, gamma=1.4, vdw_a=0.0, vdw_b=0.0, vdw_R=1.0, **_):
-    """Advance W0 ((dim+2, ny, nx) FP64) to t_end with periodic (0) or outflow
-    (1) boundaries bc = (x-low, x-high, y-low, y-high); returns (W, steps)."""
-    c = _config(dim, nx, ny, dx, bc, cfl, eos, gamma, vdw_a, vdw_b, vdw_R)
+def run(W0, dim, nx, ny, dx, bc, t_end, cfl=0.4, eos=0, gamma=1.4, vdw_a=0.0, vdw_b=0.0, vdw_R=1.0,
+        bc_state=(None, None), **_):
+    """Advance W0 ((dim+2, ny, nx) FP64) to t_end with periodic (0), outflow (1)
+    or pinned (2, x edges, state bc_state[side]) boundaries bc = (x-low, x-high,
+    y-low, y-high); returns (W, steps)."""
+    c = _config(dim, nx, ny, dx, bc, cfl, eos, gamma, vdw_a, vdw_b, vdw_R, bc_state)
     W = np.ascontiguousarray(np.array(W0, dtype=np.float64))
     steps = _get().ms_run(ctypes.byref(c), W.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(t_end))
     if steps < 0:

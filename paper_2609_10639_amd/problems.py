@@ -3,7 +3,10 @@
 This module only builds initial conditions: primitive states of the paper's
 benchmark families, converted to the conserved vector W = (rho, rho u, rho E)
 (Sec. II.A, Eqs. 1-2) through the caloric relation e(rho, P) of the chosen EOS,
-plus a counter-based random number generator.  It holds none of the method's
+plus a counter-based random number generator.  The shock-vortex problem also
+needs its exact stationary-shock states and an EOS-generic vortex; those are
+solved here from thermodynamic relations written out from the van der Waals
+model itself (isentrope, sound speed as -v^2 dP/dv along it, enthalpy).  It holds none of the method's
 arithmetic (no flux, equilibrium, sensor or time step) and both the CPU oracle
 and the GPU library consume the arrays it returns unchanged.
 
@@ -232,6 +235,139 @@ def vortex_in_stream(nx, ny, dx, speed=2.0, centre=None, strength=5.0):
     W = conserved(IDEAL_AIR, rho, speed - amp * dyp, rho * T, amp * dxp)
     W_inf = conserved(IDEAL_AIR, np.ones(1), np.full(1, speed), np.ones(1), np.zeros(1))[:, 0]
     return W, W_inf
+
+
+# --------------------------------------------------------------- shock-vortex
+
+
+def temperature(gas, rho, P):
+    """T(rho, P): ideal P/(R rho); van der Waals (P + a rho^2)(1 - b rho)/(R rho)."""
+    if gas.eos == IDEAL:
+        return P / (gas.R * rho)
+    return (P + gas.a * rho * rho) * (1.0 - gas.b * rho) / (gas.R * rho)
+
+
+def sound_speed2(gas, rho, P):
+    """c_s^2 = -v^2 (dP/dv) at constant entropy, v = 1/rho.  With constant c_v
+    the isentropes are T (v - b)^(R/c_v) = const, so for van der Waals
+    c_s^2 = gamma R T/(1 - b rho)^2 - 2 a rho, and gamma P/rho for the ideal gas."""
+    if gas.eos == IDEAL:
+        return gas.gamma * P / rho
+    T = temperature(gas, rho, P)
+    return gas.gamma * gas.R * T / (1.0 - gas.b * rho) ** 2 - 2.0 * gas.a * rho
+
+
+def enthalpy(gas, rho, P):
+    return gas.internal_energy(rho, P) + P / rho
+
+
+def isentrope_pressure(gas, rho, rho0, P0):
+    """P(rho) on the isentrope through (rho0, P0): T = T0 [(v0 - b)/(v - b)]^(R/c_v)."""
+    T0 = temperature(gas, rho0, P0)
+    b = gas.b if gas.eos == VDW else 0.0
+    T = T0 * ((1.0 / rho0 - b) / (1.0 / rho - b)) ** (gas.R / gas.cv)
+    if gas.eos == IDEAL:
+        return gas.R * rho * T
+    return gas.R * rho * T / (1.0 - gas.b * rho) - gas.a * rho * rho
+
+
+def stationary_shock(gas, rho1, P1, mach):
+    """Downstream state (rho2, u2, P2) of a stationary normal shock with
+    upstream (rho1, u1 = mach c_s1, P1) (Sec. IV.H): the root rho2 > rho1 of the
+    mass, momentum and stagnation-enthalpy jump conditions
+        rho1 u1 = rho2 u2,  rho1 u1^2 + P1 = rho2 u2^2 + P2,  h1 + u1^2/2 = h2 + u2^2/2,
+    bracketed on a fine scan of rho2 and refined by bisection.  Returns
+    (u1, (rho2, u2, P2))."""
+    u1 = mach * math.sqrt(sound_speed2(gas, rho1, P1))
+    m = rho1 * u1
+    mom = rho1 * u1 * u1 + P1
+    H = enthalpy(gas, rho1, P1) + 0.5 * u1 * u1
+
+    def resid(r2):
+        u2 = m / r2
+        return enthalpy(gas, r2, mom - m * u2) + 0.5 * u2 * u2 - H
+
+    hi = (1.0 - 1e-9) / gas.b if (gas.eos == VDW and gas.b > 0) else 20.0 * rho1
+    xs = np.linspace(rho1 * (1.0 + 1e-6), hi, 20001)
+    fs = np.array([resid(x) for x in xs])
+    k = np.nonzero(fs[:-1] * fs[1:] < 0)[0]
+    if len(k) == 0:
+        raise ValueError("no compressive shock root")
+    lo, up = xs[k[0]], xs[k[0] + 1]
+    for _ in range(200):
+        mid = 0.5 * (lo + up)
+        if resid(lo) * resid(mid) <= 0:
+            up = mid
+        else:
+            lo = mid
+    r2 = 0.5 * (lo + up)
+    return u1, (r2, m / r2, mom - m * m / r2)
+
+
+def vortex_profile(gas, rho_inf, P_inf, strength=2.0, core=1.0, r_max=12.0, h=1e-3):
+    """EOS-generic isentropic vortex (Sec. IV.H): azimuthal speed
+    u_phi = strength/(2 pi core) r exp((1 - r^2/core^2)/2) with the density from
+    d rho/dr = rho u_phi^2/(r c_s^2) along the isentrope through the far field
+    (rho_inf, P_inf), integrated inward from r_max by Heun's RK2.  Returns the
+    ascending radii and rho(r)."""
+    def uphi2_over_r(r):
+        return (strength / (2.0 * math.pi * core)) ** 2 * r * math.exp(1.0 - r * r / (core * core))
+
+    def rhs(r, rho):
+        return rho * uphi2_over_r(r) / sound_speed2(gas, rho, isentrope_pressure(gas, rho, rho_inf, P_inf))
+
+    n = int(round(r_max / h))
+    rs = np.linspace(0.0, r_max, n + 1)
+    rho = np.empty(n + 1)
+    rho[n] = rho_inf
+    for i in range(n, 0, -1):
+        r, dr = rs[i], rs[i - 1] - rs[i]
+        k1 = rhs(r, rho[i])
+        k2 = rhs(r + dr, rho[i] + dr * k1)
+        rho[i - 1] = rho[i] + 0.5 * dr * (k1 + k2)
+    return rs, rho
+
+
+# (rho1, P1) ambient states of Sec. IV.H and their runs: ideal gas and the BZT
+# van der Waals gas (a = 1, b = 0.3, R = 1, gamma = 1.02)
+BZT_GAS = Gas(VDW, 1.02, 1.0, 0.3, 1.0)
+SHOCK_VORTEX = {
+    "ideal": dict(gas=IDEAL_AIR, rho1=1.0, P1=1.0, nx=800, ny=300, t_end=7.0),
+    "bzt": dict(gas=BZT_GAS, rho1=0.70, P1=0.3787, nx=1200, ny=450, t_end=15.0),
+}
+
+
+def shock_vortex(case, nx=None, ny=None, mach=1.2, Lx=16.0, Ly=6.0, xs=6.0, centre=(2.0, 3.0), strength=2.0):
+    """Stationary normal shock at x = xs in its rest frame on [0, Lx] x [0, Ly]
+    with the upstream state for x < xs, the exact downstream state beyond, and
+    an isentropic vortex (core radius 1) centred at `centre` superposed on the
+    upstream cells only (Sec. IV.H).  Returns W, dx and the upstream conserved
+    state (the state of the pinned inflow edge)."""
+    c = SHOCK_VORTEX[case]
+    gas = c["gas"]
+    nx = nx or c["nx"]
+    ny = ny or c["ny"]
+    dx = Lx / nx
+    if abs(Ly / ny - dx) > 1e-12 * dx:
+        raise ValueError("square cells need ny/nx = Ly/Lx")
+    u1, (r2, u2, P2) = stationary_shock(gas, c["rho1"], c["P1"], mach)
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dx
+    X, Y = np.meshgrid(x, y)
+    ox, oy = X - centre[0], Y - centre[1]
+    r = np.hypot(ox, oy)
+    rs, prof = vortex_profile(gas, c["rho1"], c["P1"], strength)
+    rho_v = np.interp(r, rs, prof)
+    uphi = strength / (2.0 * math.pi) * r * np.exp(0.5 * (1.0 - r * r))
+    safe = np.maximum(r, 1e-300)
+    up = X < xs
+    rho = np.where(up, rho_v, r2)
+    u = np.where(up, u1 - uphi * oy / safe, u2)
+    v = np.where(up, uphi * ox / safe, 0.0)
+    P = np.where(up, isentrope_pressure(gas, rho_v, c["rho1"], c["P1"]), P2)
+    W = conserved(gas, rho, u, P, v)
+    W_in = conserved(gas, np.full(1, c["rho1"]), np.full(1, u1), np.full(1, c["P1"]), np.zeros(1))[:, 0]
+    return W, dx, W_in
 
 
 def vortex_perturbed(n, amplitude=1e-3, seed=42, L=10.0, strength=5.0):
