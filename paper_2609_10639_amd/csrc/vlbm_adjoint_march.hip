@@ -440,63 +440,105 @@ __global__ void __launch_bounds__(64) k_adj_march(const KParams P, const S* __re
     }
 }
 
-// Folds the wavefront records (fixed order) and adds the normaliser term
-// dJ/dM_k * sign(Q_alpha,k) at the first maximiser of each |Q_alpha,k|,
-// through the closure transpose, to lam^n.  One workgroup.
+// Folds the per-wavefront records (sum of dJ/dM_k; max |Q_alpha,k| with the
+// smallest flat index among equal maxima) and adds the normaliser term
+// dJ/dM_k * sign(Q_alpha,k) at each maximiser, through the closure transpose,
+// to lam^n.  One workgroup of 1024 threads: each folds its records, the waves combine theirs by
+// shuffles and the 16 wave results are folded in wave order, so the sums have
+// a fixed order.  Threads 0-3 evaluate the four components' terms in parallel;
+// thread 0 then applies them to lam in component order (two components may
+// share a maximiser).
+constexpr int kFixThreads = 1024;
+
 template <typename S, typename C, int EOS>
-__global__ void __launch_bounds__(256) k_adjm_fix(KParams p, const S* __restrict__ f, const double* __restrict__ rec,
-                                                  int nrec, S* __restrict__ lam_out)
+__global__ void __launch_bounds__(kFixThreads) k_adjm_fix(KParams p, const S* __restrict__ f,
+                                                          const double* __restrict__ rec, int nrec,
+                                                          S* __restrict__ lam_out)
 {
-    __shared__ double sm[4][256], sv[4][256], si[4][256];
+    constexpr int NW = kFixThreads / 64;
+    __shared__ double wm[NW][4], wv[NW][4], wi[NW][4];
+    __shared__ C wb[4][4];
+    __shared__ long long wc[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double a[4] = {0, 0, 0, 0}, v[4] = {-1, -1, -1, -1}, ix[4] = {0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nrec; b += 256)
+    for (int b = threadIdx.x; b < nrec; b += kFixThreads) {
+        const double* r = rec + (size_t)b * kRecDoubles;
+        double rr[kRecDoubles];
+#pragma unroll
+        for (int j = 0; j < kRecDoubles; ++j) rr[j] = r[j];
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const double* r = rec + (size_t)b * kRecDoubles;
-            a[k] += r[k];
-            if (r[4 + k] > v[k] || (r[4 + k] == v[k] && r[8 + k] < ix[k])) {
-                v[k] = r[4 + k];
-                ix[k] = r[8 + k];
+            a[k] += rr[k];
+            if (rr[4 + k] > v[k] || (rr[4 + k] == v[k] && rr[8 + k] < ix[k])) {
+                v[k] = rr[4 + k];
+                ix[k] = rr[8 + k];
             }
         }
-    for (int k = 0; k < 4; ++k) {
-        sm[k][threadIdx.x] = a[k];
-        sv[k][threadIdx.x] = v[k];
-        si[k][threadIdx.x] = ix[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int o = 32; o > 0; o >>= 1) {
+            a[k] += __shfl_xor(a[k], o, 64);
+            const double v2 = __shfl_xor(v[k], o, 64), i2 = __shfl_xor(ix[k], o, 64);
+            if (v2 > v[k] || (v2 == v[k] && i2 < ix[k])) {
+                v[k] = v2;
+                ix[k] = i2;
+            }
+        }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            wm[wave][k] = a[k];
+            wv[wave][k] = v[k];
+            wi[wave][k] = ix[k];
+        }
+    __syncthreads();
+    const long long ncell = (long long)p.nx * p.ny;
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        double Mb = 0.0, vm = -1.0, im = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            Mb += wm[w][k];
+            if (wv[w][k] > vm || (wv[w][k] == vm && wi[w][k] < im)) {
+                vm = wv[w][k];
+                im = wi[w][k];
+            }
+        }
+        wc[k] = -1;
+        if (Mb != 0.0 && vm >= 0.0) {
+            const long long id = (long long)im;
+            const int al = (int)(id / ncell);
+            const long long c = id % ncell;
+            const Gas<C> g = make_gas<C>(p);
+            C W[4] = {0, 0, 0, 0};
+            for (int i = 0; i < 4; ++i)
+                for (int kk = 0; kk < 4; ++kk) W[kk] += (C)f[(long long)(i * 4 + kk) * p.plane + c];
+            C u[2], e, P, Qf[2][4];
+            closure<C, EOS, 2>(g, W, u, e, P, Qf);
+            // seed Q_bar at (al, k) only; selects keep every array index static
+            C Qb[2][4], ub[2] = {0, 0}, Wb[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+                for (int k2 = 0; k2 < 4; ++k2) {
+                    const C q = Qf[a2][k2];
+                    const C sg = q > (C)0 ? (C)1 : (q < (C)0 ? (C)-1 : (C)0);
+                    Qb[a2][k2] = (a2 == al && k2 == k) ? (C)Mb * sg : (C)0;
+                }
+            closure_adj<C, EOS, 2>(g, W, Qb, ub, Wb);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) wb[k][kk] = Wb[kk];
+            wc[k] = c;
+        }
     }
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 4; ++k) {
-                sm[k][threadIdx.x] += sm[k][threadIdx.x + s];
-                const double v2 = sv[k][threadIdx.x + s], i2 = si[k][threadIdx.x + s];
-                if (v2 > sv[k][threadIdx.x] || (v2 == sv[k][threadIdx.x] && i2 < si[k][threadIdx.x])) {
-                    sv[k][threadIdx.x] = v2;
-                    si[k][threadIdx.x] = i2;
-                }
-            }
-        __syncthreads();
-    }
     if (threadIdx.x != 0) return;
-    const long long ncell = (long long)p.nx * p.ny;
-    const Gas<C> g = make_gas<C>(p);
     for (int k = 0; k < 4; ++k) {
-        const double Mb = sm[k][0];
-        if (Mb == 0.0 || sv[k][0] < 0.0) continue;
-        const long long id = (long long)si[k][0];
-        const int al = (int)(id / ncell);
-        const long long c = id % ncell;
-        C W[4] = {0, 0, 0, 0};
-        for (int i = 0; i < 4; ++i)
-            for (int kk = 0; kk < 4; ++kk) W[kk] += (C)f[(long long)(i * 4 + kk) * p.plane + c];
-        C u[2], e, P, Qf[2][4];
-        closure<C, EOS, 2>(g, W, u, e, P, Qf);
-        C Qb[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, ub[2] = {0, 0}, Wb[4] = {0, 0, 0, 0};
-        Qb[al][k] = (C)Mb * (Qf[al][k] > (C)0 ? (C)1 : (Qf[al][k] < (C)0 ? (C)-1 : (C)0));
-        closure_adj<C, EOS, 2>(g, W, Qb, ub, Wb);
+        if (wc[k] < 0) continue;
         for (int i = 0; i < 4; ++i)
             for (int kk = 0; kk < 4; ++kk) {
-                S* dst = lam_out + (long long)(i * 4 + kk) * p.plane + c;
-                *dst = (S)((C)*dst + Wb[kk]);
+                S* dst = lam_out + (long long)(i * 4 + kk) * p.plane + wc[k];
+                *dst = (S)((C)*dst + wb[k][kk]);
             }
     }
 }
@@ -519,7 +561,7 @@ static hipError_t march_t(const KParams& p, const void* f_n, const double* norms
 #define VLBM_AM(E, SN)                                                                                         \
     if (p.eos == E && p.sensor == SN) {                                                                        \
         hipLaunchKernelGGL((k_adj_march<S, C, E, SN>), dim3(nb), dim3(64), 0, st, p, f, norms, lam, lo, rec); \
-        if (SN != 0) hipLaunchKernelGGL((k_adjm_fix<S, C, E>), dim3(1), dim3(256), 0, st, p, f, rec, nb, lo);  \
+        if (SN != 0) hipLaunchKernelGGL((k_adjm_fix<S, C, E>), dim3(1), dim3(kFixThreads), 0, st, p, f, rec, nb, lo);  \
         return hipGetLastError();                                                                              \
     }
     VLBM_AM(0, 0) VLBM_AM(0, 1) VLBM_AM(0, 2) VLBM_AM(1, 0) VLBM_AM(1, 1) VLBM_AM(1, 2)
