@@ -89,6 +89,8 @@ IDEAL_AIR = Gas(IDEAL, 1.4)
 IDEAL_MONO = Gas(IDEAL, 5.0 / 3.0)
 # reduced van der Waals units rho_c = P_c = 1 (a = 3, b = 1/3, R = 1), c_v/R = 50
 VDW_REDUCED_CV50 = Gas(VDW, 1.0 + 1.0 / 50.0, 3.0, 1.0 / 3.0, 1.0)
+# the BZT van der Waals gas of Sec. IV.F and IV.H: a = 1, b = 0.3, R = 1, c_v/R = 50
+BZT_GAS = Gas(VDW, 1.02, 1.0, 0.3, 1.0)
 
 
 def conserved(gas, rho, u, P, v=None):
@@ -329,8 +331,7 @@ def vortex_profile(gas, rho_inf, P_inf, strength=2.0, core=1.0, r_max=12.0, h=1e
 
 
 # (rho1, P1) ambient states of Sec. IV.H and their runs: ideal gas and the BZT
-# van der Waals gas (a = 1, b = 0.3, R = 1, gamma = 1.02)
-BZT_GAS = Gas(VDW, 1.02, 1.0, 0.3, 1.0)
+# van der Waals gas
 SHOCK_VORTEX = {
     "ideal": dict(gas=IDEAL_AIR, rho1=1.0, P1=1.0, nx=800, ny=300, t_end=7.0),
     "bzt": dict(gas=BZT_GAS, rho1=0.70, P1=0.3787, nx=1200, ny=450, t_end=15.0),
@@ -397,13 +398,19 @@ def gresho(n, P0=5.0):
     return conserved(IDEAL_MONO, np.ones_like(X), u, P, v), dx
 
 
-# Four-quadrant states (rho, u, v, P) of the paper's 2-D Riemann problems.
+# Four-quadrant states (rho, u, v, P) of the paper's 2-D Riemann problems:
+# configurations 12 and 3 (ideal gas, Sec. IV.E) and the BZT problem (Sec. IV.F,
+# Eq. 49), with each one's gas and end time.
 RIEMANN_CONFIGS = {
     12: dict(NE=(0.5313, 0.0, 0.0, 0.4), NW=(1.0, 0.7276, 0.0, 1.0),
              SW=(0.8, 0.0, 0.0, 1.0), SE=(1.0, 0.0, 0.7276, 1.0)),
     3: dict(NE=(1.5, 0.0, 0.0, 1.5), NW=(0.5323, 1.206, 0.0, 0.3),
             SW=(0.138, 1.206, 1.206, 0.029), SE=(0.5323, 0.0, 1.206, 0.3)),
+    "bzt": dict(NE=(0.65000, 0.0, 0.0, 0.36763), NW=(1.00051, 0.15803, 0.0, 0.41396),
+                SW=(0.75000, 0.0, 0.0, 0.41396), SE=(1.00000, 0.0, -0.15747, 0.41396)),
 }
+RIEMANN_GAS = {12: IDEAL_AIR, 3: IDEAL_AIR, "bzt": BZT_GAS}
+RIEMANN_T_END = {12: 0.25, 3: 0.3, "bzt": 0.35}
 
 
 def riemann2d(n, config=3):
@@ -420,7 +427,7 @@ def riemann2d(n, config=3):
     east, north = X >= 0.5, Y >= 0.5
     for q, mask in (("NE", east & north), ("NW", ~east & north), ("SW", ~east & ~north), ("SE", east & ~north)):
         rho[mask], u[mask], v[mask], P[mask] = st[q]
-    return conserved(IDEAL_AIR, rho, u, P, v), dx
+    return conserved(RIEMANN_GAS[config], rho, u, P, v), dx
 
 
 def bzt_extrusion(n=2048, noise=0.01, seed=1234):

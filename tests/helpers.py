@@ -29,6 +29,13 @@ def riemann_case(n=128, config=3):
     return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2, **pr.SENSOR_2D, **IDEAL), 0.25
 
 
+def riemann_bzt_case(n=128):
+    """BZT four-quadrant problem (Sec. IV.F, Eq. 49) to t = 0.35, outflow, Sensor B."""
+    W0, dx = pr.riemann2d(n, "bzt")
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2, **pr.SENSOR_2D,
+                    **pr.BZT_GAS.config()), pr.RIEMANN_T_END["bzt"]
+
+
 def bzt2d_case(n=256):
     W0, dx = pr.bzt_extrusion(n)
     return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D, **VDW), 0.2

@@ -1,0 +1,155 @@
+"""Reproduce the paper's comparisons against its MUSCL-Rusanov-RK2 reference.
+
+Runs every benchmark the paper checks against an independent solver
+(Sec. IV.B-IV.H) at the paper's resolutions and prints the paper's error
+measure next to its printed value.  The VLBM side runs on the FP64 CPU oracle
+by default, or on the GPU library with --gpu (the two agree to about 1e-13
+relative, so the numbers are the same).  Not collected by pytest: the 2-D rows
+take minutes of CPU time.
+
+    python tests/reproduce_paper_tables.py [--gpu] [--only NAME ...]
+"""
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+sys.path.insert(0, HERE)
+
+from helpers import l1_errors, oracle_for, tube_config  # noqa: E402
+from oracle import core, muscl  # noqa: E402
+from paper_2609_10639_amd import problems as pr  # noqa: E402
+
+USE_GPU = False
+
+
+def vlbm_run(W0, cfg, t_end):
+    """W at t_end from the oracle or, with --gpu, the GPU library (FP64)."""
+    if USE_GPU:
+        from paper_2609_10639_amd import Solver
+        s = Solver(precision="fp64", **cfg)
+        s.init(W0)
+        s.run_to_time(t_end)
+        return s.W()
+    o = oracle_for(cfg, W0)
+    o.run_to_time(t_end)
+    return o.W()
+
+
+def onto_grid(field, n_from, n_to):
+    """Bilinear interpolation of a cell-centred field on the unit square from
+    an n_from^2 grid onto the centres of an n_to^2 grid (coordinates clamped
+    into the range of the source centres)."""
+    xs = (np.arange(n_from) + 0.5) / n_from
+    xt = np.clip((np.arange(n_to) + 0.5) / n_to, xs[0], xs[-1])
+    i = np.clip(np.searchsorted(xs, xt) - 1, 0, n_from - 2)
+    w = (xt - xs[i]) / (xs[i + 1] - xs[i])
+    rows = field[i] * (1.0 - w)[:, None] + field[i + 1] * w[:, None]
+    return rows[:, i] * (1.0 - w)[None, :] + rows[:, i + 1] * w[None, :]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def tubes():
+    printed = {"strong": dict(rho=1.39e-2, u=3.33e-2, P=7.18e-1), "I": dict(rho=1.31e-3, P=4.90e-4),
+               "II": dict(rho=6.91e-4, P=1.20e-3), "III": dict(rho=1.96e-3, P=2.52e-3)}
+    for case, n, n_ref in (("strong", 2000, 4000), ("I", 1000, 3000), ("II", 1000, 3000), ("III", 1000, 3000)):
+        W0, cfg, t_end = tube_config(case, n)
+        got = l1_errors(case, vlbm_run(W0, cfg, t_end), n, n_ref)
+        say("shock tube %-6s N=%d vs MUSCL %d:" % (case, n, n_ref),
+            "  ".join("L1(%s) %.3e (paper %.3e)" % (k, got[k], v) for k, v in printed[case].items()))
+
+
+def shu_osher():
+    from test_inflow import shu_osher_config, shu_osher_l2
+    n_ref = 10000
+    W0, dx = pr.shu_osher(n_ref)
+    W, _ = muscl.run(W0, 1, n_ref, 1, dx, (1, 1, 1, 1), 1.9, **pr.IDEAL_AIR.config())
+    ref = (pr.centres(n_ref, -5.0, 5.0)[0], W[0, 0])
+    for inflow in ("pinned", "outflow"):
+        for sensor in ("A", "0.9"):
+            errs = []
+            for n in (2000, 3000, 4000, 5000, 6000, 7000):
+                W0, cfg, t_end = shu_osher_config(n, sensor, inflow)
+                errs.append(shu_osher_l2(vlbm_run(W0, cfg, t_end), n, ref))
+            order = math.log(errs[0] / errs[-1]) / math.log(3.5)
+            say("Shu-Osher inflow %-7s %-10s L2(rho) N=2000..7000:" % (inflow, "sensor A" if sensor == "A" else "beta 0.9"),
+                " ".join("%.3e" % e for e in errs), " order %.2f" % order)
+
+
+def riemann_2d(config, printed, beta_min=None):
+    """VLBM at 800^2 interpolated onto the MUSCL run at 1000^2 (Sec. IV.E-IV.F).
+    Configuration 3 needs beta_min = 0.6 with Sensor B at this grid (with 0.7
+    it loses admissibility at t = 0.195)."""
+    n, n_ref = 800, 1000
+    t_end = pr.RIEMANN_T_END[config]
+    gas = pr.RIEMANN_GAS[config]
+    W0, dx = pr.riemann2d(n, config)
+    sensor = dict(pr.SENSOR_2D, **({} if beta_min is None else dict(beta_min=beta_min)))
+    cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2, eps_theta=1e-12, **sensor,
+               **gas.config())
+    t0 = time.time()
+    vlbm_W = vlbm_run(W0, cfg, t_end)
+    rho = vlbm_W[0]
+    t1 = time.time()
+    Wr0, dxr = pr.riemann2d(n_ref, config)
+    Wr, _ = muscl.run(Wr0, 2, n_ref, n_ref, dxr, (1, 1, 1, 1), t_end, **gas.config())
+    t2 = time.time()
+    d = onto_grid(rho, n, n_ref) - Wr[0]
+    rel = np.abs(d).sum() / np.abs(Wr[0]).sum()
+    say("Riemann %-4s VLBM 800^2 onto MUSCL 1000^2 (beta_min %.2g): rel L1(rho) %.3f %% (paper %s)  L1 %.2e L2 %.2e"
+        " Linf %.2e  [%.0f s + %.0f s]" % (config, cfg["beta_min"], 100 * rel, printed, np.abs(d).mean(),
+                                          math.sqrt((d * d).mean()), np.abs(d).max(), t1 - t0, t2 - t1))
+    if gas.eos == pr.VDW:
+        cfgo = core.make_config(**gas.config())
+        for name, W in (("VLBM", vlbm_W), ("MUSCL", Wr)):
+            r = W[0][::4, ::4].ravel()
+            e = (W[3] / W[0] - 0.5 * (W[1] ** 2 + W[2] ** 2) / W[0] ** 2)[::4, ::4].ravel()
+            neg = np.mean([core.gamma_fundamental(cfgo, float(a), float(b)) < 0 for a, b in zip(r, e)])
+            say("  Gamma < 0 on %.1f %% of the %s domain (paper 99.0 %%)" % (100 * neg, name))
+
+
+def shock_vortex(case, printed):
+    from test_shock_vortex import shock_vortex_config
+    nx = pr.SHOCK_VORTEX[case]["nx"]
+    W0, cfg, t_end = shock_vortex_config(case, nx)
+    gas = pr.SHOCK_VORTEX[case]["gas"]
+    rho = vlbm_run(W0, cfg, t_end)[0]
+    Wm, _ = muscl.run(W0, 2, cfg["nx"], cfg["ny"], cfg["dx"], cfg["bc"], t_end, bc_state=cfg["bc_state"],
+                      **gas.config())
+    rel = np.abs(rho - Wm[0]).sum() / np.abs(Wm[0]).sum()
+    say("shock-vortex %-5s %dx%d: rel L1(rho) VLBM vs MUSCL %.3f %% (paper %s)" % (case, cfg["nx"], cfg["ny"],
+                                                                                  100 * rel, printed))
+
+
+ROWS = {
+    "tubes": tubes,
+    "shu_osher": shu_osher,
+    "riemann12": lambda: riemann_2d(12, "0.15 %"),
+    "riemann3": lambda: riemann_2d(3, "0.39 %", beta_min=0.6),
+    "riemann_bzt": lambda: riemann_2d("bzt", "0.12 %"),
+    "shock_vortex_ideal": lambda: shock_vortex("ideal", "0.093 %"),
+    "shock_vortex_bzt": lambda: shock_vortex("bzt", "0.114 %"),
+}
+
+
+def main():
+    global USE_GPU
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpu", action="store_true")
+    ap.add_argument("--only", nargs="*", default=list(ROWS))
+    a = ap.parse_args()
+    USE_GPU = a.gpu
+    for name in a.only:
+        ROWS[name]()
+
+
+if __name__ == "__main__":
+    main()

@@ -18,8 +18,8 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import (bzt1d_case, bzt2d_case, energy_gauge, gresho_case, oracle_for, rel_errors, riemann_case,
-                     sod_case, speed_error, vortex_case)
+from helpers import (bzt1d_case, bzt2d_case, energy_gauge, gresho_case, oracle_for, rel_errors, riemann_bzt_case,
+                     riemann_case, sod_case, speed_error, vortex_case)
 
 pytestmark = pytest.mark.gpu
 
@@ -80,6 +80,12 @@ def test_vortex_fp64():
 @pytest.mark.parametrize("config", [3, 12])
 def test_riemann_fp64(config):
     W0, cfg, t_end = riemann_case(128, config)
+    o, n_o, s, n_g = _run_both(W0, cfg, t_end)
+    _check(o, n_o, s, n_g, t_end, 1e-9, "l1")
+
+
+def test_riemann_bzt_fp64():
+    W0, cfg, t_end = riemann_bzt_case(128)
     o, n_o, s, n_g = _run_both(W0, cfg, t_end)
     _check(o, n_o, s, n_g, t_end, 1e-9, "l1")
 
@@ -180,19 +186,20 @@ def test_vortex_fp32_sensor_b_target(precision):
 
 
 SHOCKED = {"riemann3": lambda: riemann_case(128, 3), "riemann12": lambda: riemann_case(128, 12),
-           "sod": lambda: sod_case(1000), "bzt1d": lambda: bzt1d_case(1024)}
+           "sod": lambda: sod_case(1000), "bzt1d": lambda: bzt1d_case(1024),
+           "riemann_bzt": lambda: riemann_bzt_case(128)}
 
 
 @pytest.mark.parametrize("precision", ["fp32_mixed", "fp32"])
 @pytest.mark.parametrize("case", list(SHOCKED))
 def test_shocked_fp32(case, precision):
-    """Relative L1 <= 1e-5 per field.  The dense-gas case stores its energy in
-    the shifted gauge (e_offset = mean internal energy of W0)."""
+    """Relative L1 <= 1e-5 per field.  The dense-gas cases store their energy
+    in the shifted gauge (e_offset = mean internal energy of W0)."""
     if case == "riemann12" and precision == "fp32":
         pytest.xfail("FP32 arithmetic noise in the quiescent quadrants reaches the Ducros ratio; "
                      "relative L1 ~6e-5 (FP32 storage with FP64 arithmetic meets 1e-5)")
     W0, cfg, t_end = SHOCKED[case]()
-    if case == "bzt1d":
+    if case in ("bzt1d", "riemann_bzt"):
         cfg = dict(cfg, e_offset=energy_gauge(W0))
     o, n_o, s, n_g = _run_both(W0, cfg, t_end, precision)
     assert s.clock()[0] == t_end

@@ -200,3 +200,4 @@ def test_argrow_wave_types():
     _, dr, wr = _front(rho, x, "right")
     assert dl < 0 and wl >= 100, (dl, wl)
     assert dr < 0 and wr <= 20 and beta[x > 0.5].min() < 0.9, (dr, wr)
+
