@@ -272,8 +272,11 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
     p.beta_max = cfg->beta_max;
     p.c_sensor = cfg->c_sensor;
     p.eps_theta = cfg->eps_theta;
-    // D2Q4 strips own whole 128-byte lines of every plane row
-    p.strip_w = ctx->fp32 ? 32 : 48;
+    // D2Q4 strips of 48 columns: three whole 128-byte lines in FP64; in FP32
+    // one and a half, two neighbouring strips writing the halves of a shared
+    // line within the same row sweep (measured faster than 32-column strips,
+    // which leave half of the 64 lanes to the halo)
+    p.strip_w = 48;
     if (const char* env = getenv("VLBM_STRIP_W")) {
         const int v = atoi(env);
         if (v >= 8 && v <= 58 && v % 2 == 0) p.strip_w = v;

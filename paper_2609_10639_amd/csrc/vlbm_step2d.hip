@@ -1,9 +1,12 @@
 // Fused D2Q4 VLBM time step for gfx950 (arXiv 2609.10639, Sec. III).
 //
 // One wavefront owns a strip of output columns and marches up a segment of
-// rows.  The strip is a whole number of 128-byte lines (48 FP64 or 32 FP32
-// columns, aligned), so that every store fills complete L2 lines: partially
-// written lines cost HBM bandwidth far beyond their size.  The 64 lanes hold
+// rows.  The strip is 48 columns: three whole 128-byte lines in FP64, so every
+// store fills complete L2 lines (partially written lines cost HBM bandwidth far
+// beyond their size); one and a half lines in FP32, where two neighbouring
+// strips write the halves of the shared line in the same row sweep and the
+// halves merge in L2 (measured faster than 32-column strips, which give half of
+// the lanes to the halo).  The 64 lanes hold
 // 64 consecutive columns centred on the strip (the stencil needs 3 halo
 // columns on each side); x-neighbour values move between lanes through the LDS crossbar
 // (ds_bpermute); the raw populations of the last three rows sit in a per-wave
@@ -58,7 +61,12 @@ struct March {
     C J[3][4], Dl[3], Vo[3];   // partial sums of j_k, dilatation, vorticity
     C Ss[3], Sth[3];           // S_x[s], S_x[theta]
     C yprev[4], wpend[4];      // f*_{+y} of the last collided row, pending moments of the row below
-    S pre[16];                 // populations of the next row to enter the march (loads in flight)
+    // Rows in flight: with DEPTH 1 buf[0] holds the loads of row R+1 while row R
+    // is processed; with DEPTH 2 (FP32 storage: registers to spare) three buffers
+    // rotate with the unrolled phase, row R in buf[PH] and the loads of rows R+1
+    // and R+2 in the other two, so twice the bytes are in flight per wavefront.
+    static constexpr int DEPTH = sizeof(S) == 4 ? 2 : 1;
+    S buf[DEPTH == 2 ? 3 : 1][16];
     // reductions of the new state: maxima, and the admissibility witnesses
     C red_s, red_M[4];
     int ebits;                 // admissibility of the new state: ERR_NONHYP | ERR_NONFINITE
@@ -94,14 +102,20 @@ struct March {
     __device__ __forceinline__ void iter(int R)
     {
         constexpr int cR = PH, cR1 = (PH + 2) % 3, cR2 = (PH + 1) % 3, cR3 = PH, cR4 = (PH + 2) % 3;
-        // ---------------- row R arrived during the previous row; issue the loads of row R+1.
-        // The load is unconditional (past the last row it re-reads row Re, in bounds): a
-        // conditional load would merge into pre through copies that wait for the data at once.
+        // ---------------- row R arrived during the previous rows; issue the loads of row
+        // R+DEPTH.  The load is unconditional (past the last row it re-reads row Re, in
+        // bounds): a conditional load would merge into the buffer through copies that wait
+        // for the data at once.
         const bool hasA = R <= Re;
-        S fa[16];
+        S fa1[16];
+        if constexpr (DEPTH == 1) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) fa[j] = pre[j];
-        load_row(min(R + 1, Re), pre);
+            for (int j = 0; j < 16; ++j) fa1[j] = buf[0][j];
+            load_row(min(R + 1, Re), buf[0]);
+        } else {
+            load_row(min(R + 2, Re), buf[(PH + 2) % 3]);
+        }
+        const S(&fa)[16] = DEPTH == 1 ? fa1 : buf[DEPTH == 1 ? 0 : PH];
 
         // ---------------- stage C: row p = R-3 (LDS slot cR3)
         const int p = R - 3;
@@ -371,7 +385,10 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
     m.red_s = (C)0;
     m.ebits = 0;
 
-    if (m.Rb <= m.Re) m.load_row(m.Rb, m.pre);
+    if (m.Rb <= m.Re) {
+        m.load_row(m.Rb, m.buf[0]);
+        if constexpr (decltype(m)::DEPTH == 2) m.load_row(min(m.Rb + 1, m.Re), m.buf[1]);
+    }
     const int Rlast = m.y1 + 3;
     // every wavefront of the workgroup runs the same rows (same segment), so the
     // barriers are reached uniformly
