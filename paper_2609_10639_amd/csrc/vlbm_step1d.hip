@@ -1,13 +1,16 @@
 // Fused D1Q2 VLBM time step for gfx950 (arXiv 2609.10639, Sec. III).
 //
 // A 256-thread workgroup processes tiles of 256 consecutive cells (grid-stride
-// over the tiles, at most 1024 workgroups).  It stages the 262 cells of a tile
+// over the tiles, at most 1024 workgroups with FP64 storage and 4096 with FP32
+// storage, whose tiles carry half the bytes: measured best on MI355X).  It stages the 262 cells of a tile
 // plus a 3-cell halo in LDS and runs the step in four barrier-separated phases:
 //   A  load the 6 populations (SoA planes, coalesced), reproject to the new
 //      link speed (Sec. III.E, D = 1 form of Eq. 40), flux Q(W) (Eq. 10);
 //   B  normalised flux-divergence activity s (Eqs. 28-31);
 //   C  box filter, beta (Sensor A, Eq. 34), over-relaxation (Eqs. 20, 22);
 //   D  pull-streaming (Eq. 21), store, and the reductions of the new state.
+#include <cstdlib>
+
 #include "vlbm_common.hpp"
 
 namespace vlbm {
@@ -15,7 +18,8 @@ namespace vlbm {
 constexpr int kTile1 = 256;
 constexpr int kHalo1 = 3;
 constexpr int kSlots1 = kTile1 + 2 * kHalo1;
-constexpr int kGrid1 = 1024;   // blocks per launch (4 per CU); each strides over the tiles
+constexpr int kGrid1 = 1024;   // blocks per launch, FP64 storage (4 per CU); each strides over the tiles
+constexpr int kGrid1F = 4096;  // the same with FP32 storage (16 per CU)
 
 template <typename ST, typename T, int EOS, int SENSOR>
 __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep S, const ST* __restrict__ fin,
@@ -176,7 +180,12 @@ template <typename ST, typename T>
 static hipError_t launch_t(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
 {
     const int ntiles = (p.nx + kTile1 - 1) / kTile1;
-    const dim3 grid(ntiles < kGrid1 ? ntiles : kGrid1), block(kTile1);
+    int gmax = sizeof(ST) == 4 ? kGrid1F : kGrid1;
+    if (const char* env = getenv("VLBM_D1_GRID")) {   // tuning override
+        const int v = atoi(env);
+        if (v >= 64 && v <= 65536) gmax = v;
+    }
+    const dim3 grid(ntiles < gmax ? ntiles : gmax), block(kTile1);
     const ST* in = (const ST*)fin;
     ST* out = (ST*)fout;
 #define VLBM_CASE(E, SN)                                                                      \
