@@ -18,7 +18,9 @@ Beside it on the same JSON line:
                 arithmetic) on the same grid;
   grid_4096     FP64 and FP32 at 4096^2, a working set far above the 256 MB
                 last-level cache (the grid for roofline claims);
-  riemann4096   four-quadrant Riemann configuration 3, 4096^2, FP32, outflow;
+  riemann4096   four-quadrant Riemann configuration 3, 4096^2, outflow, Sensor A
+                (the Ducros gate of Sensor B loses admissibility at this grid):
+                per-step rates, and the whole FP32 run to t = 0.25;
   d1q2          the D1Q2 step (Sod shock tube data) at 2^26 cells;
   adjoint       adjoint/forward step-cost ratio on the adjoint workload
                 (1024^2 perturbed vortex, frozen dt = 1/625, Sensor B), per
@@ -66,10 +68,31 @@ def vortex_cfg(n):
 
 
 def riemann_cfg(n):
+    """Configuration 3 with Sensor A (0.7, 1, 16): with the Ducros gate of
+    Sensor B it loses admissibility on grids from 800^2 up."""
     from paper_2609_10639_amd import problems as pr
     W0, dx = pr.riemann2d(n, 3)
-    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2, **pr.SENSOR_2D,
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=1, **pr.SENSOR_2D,
                     **pr.IDEAL_AIR.config())
+
+
+def whole_run(W0, cfg, precision, t_end):
+    """One run from W0 to t_end (every step retargeted, landing exactly), timed
+    by the host clock around run_to_time: the whole-job rate, batches and their
+    host read-backs included."""
+    import torch
+    from paper_2609_10639_amd import Solver
+    s = Solver(precision=precision, **cfg)
+    s.init(W0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = s.run_to_time(t_end)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert s.clock()[0] == t_end
+    s.close()
+    cells = cfg["nx"] * cfg["ny"]
+    return {"t_end": t_end, "steps": n, "seconds": round(dt, 3), "MLUPS": round(n * cells / dt / 1e6, 1)}
 
 
 def sod_cfg(n):
@@ -312,6 +335,7 @@ def main():
         del Wb
         Wr, cr = riemann_cfg(nb)
         out["riemann%d" % nb] = {p: line(time_steps(Wr, cr, p, ksteps, 5), nb * nb, 2, p) for p in ("fp32", "fp64")}
+        out["riemann%d" % nb]["fp32_to_t_end"] = whole_run(Wr, cr, "fp32", 0.25)
         del Wr
         W1, c1 = sod_cfg(1 << 26)
         out["d1q2"] = {"cells": 1 << 26, **{p: line(time_steps(W1, c1, p, ksteps, 5), 1 << 26, 1, p)

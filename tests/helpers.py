@@ -24,9 +24,12 @@ def vortex_case(n=128):
     return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D, **IDEAL), 10.0
 
 
-def riemann_case(n=128, config=3):
+def riemann_case(n=128, config=3, sensor=2):
+    """Four-quadrant problem to t = 0.25 with Sensor B, or with Sensor A (no
+    Ducros gate) for configuration 3 on fine grids, where the gate loses
+    admissibility (from 800^2 up)."""
     W0, dx = pr.riemann2d(n, config)
-    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2, **pr.SENSOR_2D, **IDEAL), 0.25
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=sensor, **pr.SENSOR_2D, **IDEAL), 0.25
 
 
 def riemann_bzt_case(n=128):
