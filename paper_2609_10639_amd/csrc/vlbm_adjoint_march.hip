@@ -532,15 +532,32 @@ __global__ void __launch_bounds__(kFixThreads) k_adjm_fix(KParams p, const S* __
         }
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    // one thread per population plane: the terms of components that share a
+    // maximiser are summed in component order, then each distinct cell is read
+    // and written once (all loads issued before the stores)
+    if (threadIdx.x >= 16) return;
+    const int plane = threadIdx.x, kk = plane & 3;
+    bool use[4];
+    C add[4];
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (wc[k] < 0) continue;
-        for (int i = 0; i < 4; ++i)
-            for (int kk = 0; kk < 4; ++kk) {
-                S* dst = lam_out + (long long)(i * 4 + kk) * p.plane + wc[k];
-                *dst = (S)((C)*dst + wb[k][kk]);
-            }
+        bool first = wc[k] >= 0;
+#pragma unroll
+        for (int k2 = 0; k2 < k; ++k2) first = first && wc[k2] != wc[k];
+        C a = (C)0;
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+            if (k2 >= k && wc[k2] == wc[k]) a += wb[k2][kk];
+        use[k] = first;
+        add[k] = a;
     }
+    S* base = lam_out + (long long)plane * p.plane;
+    S old[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) old[k] = base[use[k] ? wc[k] : 0];   // cell 0 stands in when unused
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (use[k]) base[wc[k]] = (S)((C)old[k] + add[k]);
 }
 
 int adjoint_march_records(const KParams& p) { return p.nstrips * p.nsegs; }
