@@ -389,15 +389,16 @@ def test_bad_configs_rejected():
 # ------------------------------------------------------------------ full-size configurations
 
 
-@pytest.mark.parametrize("name,precision,steps", [("vortex1024", "fp64", 4), ("vortex1024", "fp32_mixed", 4),
-                                                  ("vortex1024", "fp32", 4), ("riemann4096", "fp32_mixed", 2), ("riemann4096", "fp32", 2),
-                                                  ("riemann4096", "fp64", 2), ("bzt2048", "fp64", 3),
-                                                  ("bzt8192", "fp64", 40)])
+@pytest.mark.parametrize("name,precision,steps", [
+    ("vortex1024", "fp64", 4), ("vortex1024", "fp32_mixed", 4), ("vortex1024", "fp32", 4),
+    ("riemann4096", "fp32_mixed", 2), ("riemann4096", "fp32", 2), ("riemann4096", "fp64", 2),
+    ("bzt2048", "fp64", 3), ("bzt8192", "fp64", 40), ("sod2p26", "fp64", 3), ("sod2p26", "fp32", 3)])
 def test_full_size_against_oracle(name, precision, steps):
     """At the benchmark sizes and launch configuration: a few steps compared
     with the oracle over the whole grid."""
     case = {"vortex1024": lambda: vortex_case(1024), "riemann4096": lambda: riemann_case(4096, 3, sensor=1),
-            "bzt2048": lambda: bzt2d_case(2048), "bzt8192": lambda: bzt1d_case(8192)}[name]
+            "bzt2048": lambda: bzt2d_case(2048), "bzt8192": lambda: bzt1d_case(8192),
+            "sod2p26": lambda: sod_case(1 << 26)}[name]
     W0, cfg, _ = case()
     _say("full size", name, precision, steps)
     o = oracle_for(cfg, W0)
