@@ -43,6 +43,9 @@ struct AdjMarch {
     const KParams& P;
     Planes fin, lin, lout;      // f^n, lam^{n+1}, lam^n
     C (*wr)[4][64];             // W of the last five rows (LDS ring)
+    C (*hr)[9][64];             // j_k, dil, vort, s and the x-filtered s and theta of the last three
+                                // completed rows (LDS ring): written when row R-1 completes, read by
+                                // stage C (rows R-2, R-3) and stage D (row R-3)
     Gas<C> g;
     C inv2c, inv2dx, invM[4], csen, bspan, bmax, eps;
     int nx, ny, y0, y1, Rb, Re;
@@ -52,10 +55,9 @@ struct AdjMarch {
     unsigned colx;
     bool owner, atL, atR;       // atL / atR: the clamped first / last column
 
-    // sensor forward: partial sums of rows R+1 (n), R, R-1, R-2, R-3
-    C Jn[4], J0[4], J1[4], J2[4], J3[4];
-    C Dn, D0, D1, D2, D3, Vn, V0, V1, V2, V3;
-    C s2, s3, Ss2, Ss3, Th2, Th3;   // s and the x-filtered s, theta of rows R-2, R-3
+    // sensor forward: partial sums of rows R+1 (n), R, R-1 (older rows live in hr)
+    C Jn[4], J0[4], J1[4];
+    C Dn, D0, D1, Vn, V0, V1;
     // dJ/dbeta of rows R (partial), R-1, R-2; g_{+y} and lam_{-y} of row R-1
     C bb0, bb1, bb2, gyp[4], lym[4];
     C bq1, bq2;                 // beta of rows R-3, R-4
@@ -69,6 +71,7 @@ struct AdjMarch {
     double aidx[4];
 
     __device__ __forceinline__ bool row_ok(int r) const { return !(clo && r < 0) && !(chi && r > ny - 1); }
+    __device__ __forceinline__ int hslot(int r) const { return (r - Rb + 3) % 3; }   // r >= Rb - 3
     __device__ __forceinline__ unsigned row_off(int r) const
     {
         const int m = (r < 0 || r >= ny) ? wrap_index(r, ny) : r;
@@ -197,12 +200,20 @@ struct AdjMarch {
                     acc = fma(sh, sh, acc);
                 }
                 s1 = acc > (C)0 ? sqrt(acc * (C)0.25) : (C)0;
+                const int hs = hslot(R - 1);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) hr[hs][k][lane] = J1[k];
+                hr[hs][4][lane] = D1;
+                hr[hs][5][lane] = V1;
+                hr[hs][6][lane] = s1;
                 Ss1 = (C)0.25 * shfl(s1, lnb) + (C)0.5 * s1 + (C)0.25 * shfl(s1, rnb);
                 if constexpr (SENSOR == 2) {
                     const C d2 = D1 * D1;
                     const C th = d2 / (fma(V1, V1, d2) + eps);
                     Th1 = (C)0.25 * shfl(th, lnb) + (C)0.5 * th + (C)0.25 * shfl(th, rnb);
                 }
+                hr[hs][7][lane] = Ss1;
+                hr[hs][8][lane] = Th1;
             }
         }
 
@@ -211,11 +222,16 @@ struct AdjMarch {
         if constexpr (SENSOR != 0) {
             const int p = R - 2;
             if (row_ok(p)) {
-                const C sm = (clo && p == 0) ? Ss2 : Ss3, sp = (chi && p == ny - 1) ? Ss2 : Ss1;
+                const int h2 = hslot(p), h3 = hslot(p - 1);
+                const C Ss2 = hr[h2][7][lane], Th2 = hr[h2][8][lane];
+                const bool pb = clo && p == 0, pt = chi && p == ny - 1;
+                // row p-1 below a clamped bottom is never read (its slot may hold older rows)
+                const C Ss3 = pb ? Ss2 : hr[h3][7][lane], Th3 = pb ? Th2 : hr[h3][8][lane];
+                const C sm = pb ? Ss2 : Ss3, sp = pt ? Ss2 : Ss1;
                 const C sbar = (C)0.25 * sm + (C)0.5 * Ss2 + (C)0.25 * sp;
                 C thbar = (C)1;
                 if constexpr (SENSOR == 2) {
-                    const C tm = (clo && p == 0) ? Th2 : Th3, tp = (chi && p == ny - 1) ? Th2 : Th1;
+                    const C tm = pb ? Th2 : Th3, tp = pt ? Th2 : Th1;
                     thbar = (C)0.25 * tm + (C)0.5 * Th2 + (C)0.25 * tp;
                 }
                 const C Xv = csen * sbar * thbar;
@@ -223,7 +239,6 @@ struct AdjMarch {
                 bnew = bmax - bspan * chiv;
                 const C chibar = (Xv > (C)0 && Xv < (C)1) ? -bspan * bb2 : (C)0;
                 const C ax = tbox_x(csen * thbar * chibar);
-                const bool pb = clo && p == 0, pt = chi && p == ny - 1;
                 const C qa = (C)0.25 * ax;
                 SAm += pb ? (C)0 : qa;
                 SA0 += (C)0.5 * ax + (pb ? qa : (C)0) + (pt ? qa : (C)0);
@@ -243,12 +258,14 @@ struct AdjMarch {
         if constexpr (SENSOR != 0) {
             const int q = R - 3;
             if (row_ok(q)) {
+                const int hs = hslot(q);
+                const C s3 = hr[hs][6][lane];
                 C jb[4] = {0, 0, 0, 0};
                 if (s3 > (C)0) {
                     const C f4s = SAm / ((C)4 * s3);
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const C shat = J3[k] * invM[k];
+                        const C shat = hr[hs][k][lane] * invM[k];
                         const C shb = f4s * shat;   // d s / d s_hat_k = s_hat_k / (4 s)
                         jb[k] = shb * invM[k];
                         if (owner && q >= y0 && q < y1) mbar[k] -= (double)(shb * shat * invM[k]);
@@ -256,6 +273,7 @@ struct AdjMarch {
                 }
                 C dilb = 0, vortb = 0;
                 if constexpr (SENSOR == 2) {
+                    const C D3 = hr[hs][4][lane], V3 = hr[hs][5][lane];
                     const C den = D3 * D3 + V3 * V3 + eps;
                     const C iden2 = (C)1 / (den * den);
                     dilb = TBm * (C)2 * D3 * (V3 * V3 + eps) * iden2;
@@ -331,17 +349,14 @@ struct AdjMarch {
         if constexpr (SENSOR != 0) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                J3[k] = J2[k]; J2[k] = J1[k]; J1[k] = J0[k]; J0[k] = Jn[k];
+                J1[k] = J0[k]; J0[k] = Jn[k];
                 QYm[k] = QY0[k]; QY0[k] = QYp[k]; QYp[k] = 0;
                 QXh[k] = QX[k];
                 gyp[k] = gy_p[k];
                 lym[k] = ly_m[k];
             }
-            D3 = D2; D2 = D1; D1 = D0; D0 = Dn;
-            V3 = V2; V2 = V1; V1 = V0; V0 = Vn;
-            s3 = s2; s2 = s1;
-            Ss3 = Ss2; Ss2 = Ss1;
-            Th3 = Th2; Th2 = Th1;
+            D1 = D0; D0 = Dn;
+            V1 = V0; V0 = Vn;
             bb2 = bb1; bb1 = bb0;
             bq2 = bq1; bq1 = bnew;
             SAm = SA0; SA0 = SAp; SAp = 0;
@@ -360,11 +375,18 @@ __global__ void __launch_bounds__(64) k_adj_march(const KParams P, const S* __re
                                                   double* __restrict__ rec)
 {
     __shared__ C wring[5][4][64];
+    __shared__ C hring[3][9][64];
     AdjMarch<S, C, EOS, SENSOR> m{P};
     m.fin = make_planes(f, (unsigned)P.plane);
     m.lin = make_planes(lam, (unsigned)P.plane);
     m.lout = make_planes((const S*)lam_out, (unsigned)P.plane);
     m.wr = wring;
+    m.hr = hring;
+    // rows before the first completed one read as zeros (each lane owns its column)
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl)
+#pragma unroll
+        for (int v = 0; v < 9; ++v) hring[sl][v][threadIdx.x] = (C)0;
     m.g = make_gas<C>(P);
     m.inv2c = (C)(0.5 / P.c_fixed);
     m.inv2dx = (C)(0.5 / P.dx);
@@ -403,15 +425,14 @@ __global__ void __launch_bounds__(64) k_adj_march(const KParams P, const S* __re
     m.Re = m.chi ? min(m.y1 + 3, m.ny - 1) : m.y1 + 3;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        m.Jn[k] = m.J0[k] = m.J1[k] = m.J2[k] = m.J3[k] = 0;
+        m.Jn[k] = m.J0[k] = m.J1[k] = 0;
         m.QYm[k] = m.QY0[k] = m.QYp[k] = m.QXh[k] = 0;
         m.gyp[k] = m.lym[k] = 0;
         m.mbar[k] = 0.0;
         m.amax[k] = (C)-1;
         m.aidx[k] = 0.0;
     }
-    m.Dn = m.D0 = m.D1 = m.D2 = m.D3 = m.Vn = m.V0 = m.V1 = m.V2 = m.V3 = 0;
-    m.s2 = m.s3 = m.Ss2 = m.Ss3 = m.Th2 = m.Th3 = 0;
+    m.Dn = m.D0 = m.D1 = m.Vn = m.V0 = m.V1 = 0;
     m.bb0 = m.bb1 = m.bb2 = 0;
     m.bq1 = m.bq2 = (C)P.beta_const;
     m.SAm = m.SA0 = m.SAp = m.TBm = m.TB0 = m.TBp = 0;
