@@ -279,7 +279,7 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
     p.strip_w = 48;
     if (const char* env = getenv("VLBM_STRIP_W")) {
         const int v = atoi(env);
-        if (v >= 8 && v <= 58 && v % 2 == 0) p.strip_w = v;
+        if (v >= 8 && v <= 50 && v % 2 == 0) p.strip_w = v;   // the step's LDS ring covers halos >= 7
     }
     p.nstrips = (p.nx + p.strip_w - 1) / p.strip_w;
     // adjacent strips per workgroup (measured on MI355X): 2 FP64 wavefronts

@@ -41,13 +41,20 @@ namespace vlbm {
 // this step's link speed (written once per workgroup before the march).
 __shared__ double vlbm_pin_lds[8];
 
+// The LDS ring keeps lanes kRingLo .. kRingLo + kRingW - 1 only: stage C needs
+// the raw populations of the lanes whose post-collision populations stream into
+// owned columns, lanes halo-1 .. 64-halo, within that span for strips of at
+// most 50 columns (halo >= 7).  Twelve fewer lanes let eight FP64 wavefronts
+// per CU fit in LDS instead of six.
+constexpr int kRingLo = 6, kRingW = 52;
+
 template <typename S, typename C, int EOS, int SENSOR>
 struct March {
     // uniform
     const KParams& P;
     const KStep& St;
     Planes in, out;
-    S (*ring)[16][64];
+    S (*ring)[16][kRingW];
     Gas<C> g;
     C r, inv2c, inv2dx, invM[4];
     C eoff;            // energy gauge of the stored populations (physical e = e_stored + eoff)
@@ -55,6 +62,7 @@ struct March {
     bool clo, chi;
     // per lane
     int lane, lnb, rnb, X;
+    int rl;            // this lane's ring column (clamped; lanes outside the span never write)
     unsigned colx;     // column loaded by this lane
     bool owner;
     // row-indexed histories, slot = (row - Rb) % 3
@@ -143,8 +151,8 @@ struct March {
                 C Sx[4], Dx[4], Sy[4], Dy[4], W[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const C a0 = (C)ring[cR3][0 * 4 + k][lane], a1 = (C)ring[cR3][1 * 4 + k][lane];
-                    const C a2 = (C)ring[cR3][2 * 4 + k][lane], a3 = (C)ring[cR3][3 * 4 + k][lane];
+                    const C a0 = (C)ring[cR3][0 * 4 + k][rl], a1 = (C)ring[cR3][1 * 4 + k][rl];
+                    const C a2 = (C)ring[cR3][2 * 4 + k][rl], a3 = (C)ring[cR3][3 * 4 + k][rl];
                     Sx[k] = a0 + a1;
                     Dx[k] = a0 - a1;
                     Sy[k] = a2 + a3;
@@ -235,8 +243,9 @@ struct March {
 
         // ---------------- stage A: row R (LDS slot cR)
         if (hasA) {
+            if (lane >= kRingLo && lane < kRingLo + kRingW)
 #pragma unroll
-            for (int j = 0; j < 16; ++j) ring[cR][j][lane] = fa[j];
+                for (int j = 0; j < 16; ++j) ring[cR][j][rl] = fa[j];
             if constexpr (SENSOR != 0) {
                 C W[4];
 #pragma unroll
@@ -315,7 +324,7 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
                                                    S* __restrict__ fout)
 {
     const int wave = threadIdx.x >> 6;
-    S (*ring)[16][64] = reinterpret_cast<S (*)[16][64]>(vlbm_step_lds) + 3 * wave;
+    S (*ring)[16][kRingW] = reinterpret_cast<S (*)[16][kRingW]>(vlbm_step_lds) + 3 * wave;
 
     double c_old, c_new, t, dt;
     bool last;
@@ -351,6 +360,7 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
     m.nx = P.nx;
     m.ny = P.ny;
     m.lane = threadIdx.x & 63;
+    m.rl = min(max(m.lane - kRingLo, 0), kRingW - 1);
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int group = tile % P.ngroups, seg = tile / P.ngroups;
     const int strip = group * P.wpg + wave;   // past the last strip: a wavefront that owns nothing
@@ -421,7 +431,7 @@ template <typename S, typename C>
 static hipError_t launch_t(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
 {
     const dim3 grid(p.ngroups * p.nsegs), block(64 * p.wpg);
-    const size_t lds = (size_t)p.wpg * 3 * 16 * 64 * sizeof(S);
+    const size_t lds = (size_t)p.wpg * 3 * 16 * kRingW * sizeof(S);
     const S* in = (const S*)fin;
     S* out = (S*)fout;
 #define VLBM_CASE(E, SN)                                                                       \
@@ -449,7 +459,7 @@ int step_d2q4_blocks_per_cu(const KParams& p, int prec)
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
     const int bs = 64 * p.wpg;
-    const size_t l8 = (size_t)p.wpg * 3 * 16 * 64 * 8, l4 = l8 / 2;
+    const size_t l8 = (size_t)p.wpg * 3 * 16 * kRingW * 8, l4 = l8 / 2;
     switch (prec) {
     case PREC_FP64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, double, 0, 2>, bs, l8); break;
     case PREC_FP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, float, 0, 2>, bs, l4); break;
