@@ -310,17 +310,24 @@ def test_conservation_periodic(precision):
     assert worst <= (1e-6 if precision != "fp64" else 1e-13)
 
 
-def test_tilings_agree_bitwise(monkeypatch):
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_mixed"])
+def test_tilings_agree_bitwise(monkeypatch, precision):
+    """Segment height, strip width and wavefronts per workgroup change only
+    which wavefront computes a cell: the populations agree bit for bit (the
+    reductions are maxima, exact in any order)."""
     W0, cfg, _ = riemann_case(200, 3)
     outs = []
-    for h in ("16", "37", "200"):
+    for h, w, g in (("16", "48", "1"), ("37", "48", "2"), ("200", "32", "4"), ("23", "50", "3"), ("16", "16", "2")):
         monkeypatch.setenv("VLBM_SEG_H", h)
-        s = _solver(cfg)
+        monkeypatch.setenv("VLBM_STRIP_W", w)
+        monkeypatch.setenv("VLBM_WPG", g)
+        s = _solver(cfg, precision)
         s.init(W0)
         s.step(30)
         outs.append(s.f())
         s.close()
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
 
 
 def test_deterministic_repeat():
