@@ -216,28 +216,32 @@ def adjoint_ratio(precision, n=1024, nsteps=625, reps=50):
     e1.record(s.stream)
     torch.cuda.synchronize()
     t_adj = e0.elapsed_time(e1) / reps
-    # end to end: checkpointed forward, then backward (replay + adjoint); the
-    # second of two passes is reported (the first also fills torch's caching
-    # allocator with the checkpoint and segment buffers)
-    run = Rollout(s, nsteps)
+    # end to end: checkpointed forward, then backward (replay + adjoint), with
+    # the replay overlapped on a second stream (default) and serial; the second
+    # of two passes is reported (the first also fills torch's caching allocator
+    # with the checkpoint and segment buffers)
     rho_t = torch.tensor(W0[0], device="cuda")
-    for _ in range(2):
-        ck = None
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        WN, ck = run.forward(W)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        WNbar = torch.zeros_like(WN)
-        WNbar[0] = (WN[0] - rho_t) * cfg["dx"] ** 2
-        run.backward(W, ck, WNbar)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
+    e2e = {}
+    for overlap in (True, False):
+        run = Rollout(s, nsteps, overlap=overlap)
+        for _ in range(2):
+            ck = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            WN, ck = run.forward(W)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            WNbar = torch.zeros_like(WN)
+            WNbar[0] = (WN[0] - rho_t) * cfg["dx"] ** 2
+            run.backward(W, ck, WNbar)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        e2e["end_to_end" if overlap else "end_to_end_serial"] = {
+            "steps": nsteps, "checkpoint_every": run.K, "forward_s": round(t1 - t0, 4),
+            "backward_s": round(t2 - t1, 4), "ratio": round((t2 - t1) / (t1 - t0), 3)}
     s.close()
     return {"precision": precision, "grid": [n, n], "fwd_ms_per_step": round(t_fwd, 5),
-            "adj_ms_per_step": round(t_adj, 5), "step_ratio": round(t_adj / t_fwd, 3),
-            "end_to_end": {"steps": nsteps, "checkpoint_every": run.K, "forward_s": round(t1 - t0, 4),
-                           "backward_s": round(t2 - t1, 4), "ratio": round((t2 - t1) / (t1 - t0), 3)}}
+            "adj_ms_per_step": round(t_adj, 5), "step_ratio": round(t_adj / t_fwd, 3), **e2e}
 
 
 def cpu_baseline(n, steps):

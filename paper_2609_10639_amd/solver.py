@@ -67,6 +67,10 @@ class Solver:
 
     # ------------------------------------------------------------ lifecycle
     def close(self):
+        side = getattr(self, "_rollout_side", None)   # second context of an overlapped adjoint rollout
+        if side is not None:
+            self._rollout_side = None
+            side[1].close()
         if getattr(self, "_h", None) is not None:
             N.lib().vlbm_destroy(self._h)
             self._h = None
