@@ -272,18 +272,16 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
     p.beta_max = cfg->beta_max;
     p.c_sensor = cfg->c_sensor;
     p.eps_theta = cfg->eps_theta;
-    // D2Q4 strips of 48 columns: three whole 128-byte lines in FP64; in FP32
-    // one and a half, two neighbouring strips writing the halves of a shared
-    // line within the same row sweep (measured faster than 32-column strips,
-    // which leave half of the 64 lanes to the halo)
-    p.strip_w = 48;
+    // D2Q4 strips of 56 columns (4 halo lanes a side); measured faster than 48
+    // columns (three whole FP64 lines, but 16 halo lanes), and than 32
+    p.strip_w = 56;
     if (const char* env = getenv("VLBM_STRIP_W")) {
         const int v = atoi(env);
-        if (v >= 8 && v <= 50 && v % 2 == 0) p.strip_w = v;   // the step's LDS ring covers halos >= 7
+        if (v >= 8 && v <= 56 && v % 2 == 0) p.strip_w = v;   // the step's LDS ring covers halos >= 4
     }
     p.nstrips = (p.nx + p.strip_w - 1) / p.strip_w;
     // adjacent strips per workgroup (measured on MI355X): 2 FP64 wavefronts
-    // (24 KB of LDS ring each); with FP32 storage 4 on large grids, where the
+    // (22 KB of LDS ring each); with FP32 storage 4 on large grids, where the
     // shared halo lines save HBM traffic, and 1 below 4M cells, where the march
     // is latency-bound and the per-row barrier costs more than it saves
     p.wpg = ctx->prec == PREC_FP64 ? 2 : (p.nx * (long long)p.ny >= (1LL << 22) ? 4 : 1);

@@ -22,7 +22,7 @@ struct KParams {
     int retarget_every;
     int sensor;               // resolved: 0 off, 1 A (no gate), 2 B (Ducros gate)
     double beta_const, beta_min, beta_max, c_sensor, eps_theta;
-    int strip_w;              // D2Q4: output columns per wavefront (48; halo lanes (64 - strip_w)/2 a side)
+    int strip_w;              // D2Q4: output columns per wavefront (56; halo lanes (64 - strip_w)/2 a side)
     int nstrips, seg_h, nsegs; // D2Q4 tiling: strips of columns x segments of rows
     int wpg, ngroups;         // D2Q4 step: wavefronts (adjacent strips) per workgroup, strip groups
 };

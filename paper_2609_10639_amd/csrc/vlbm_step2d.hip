@@ -1,12 +1,12 @@
 // Fused D2Q4 VLBM time step for gfx950 (arXiv 2609.10639, Sec. III).
 //
 // One wavefront owns a strip of output columns and marches up a segment of
-// rows.  The strip is 48 columns: three whole 128-byte lines in FP64, so every
-// store fills complete L2 lines (partially written lines cost HBM bandwidth far
-// beyond their size); one and a half lines in FP32, where two neighbouring
-// strips write the halves of the shared line in the same row sweep and the
-// halves merge in L2 (measured faster than 32-column strips, which give half of
-// the lanes to the halo).  The 64 lanes hold
+// rows.  The strip is 56 columns, with 4 halo lanes on each side: the
+// stencil chain needs 3 halo columns and streaming one more.  56 columns are
+// three and a half 128-byte lines in FP64 and one and three quarters in FP32;
+// the strips that share a line write their parts of it in the same row sweep
+// and the parts merge in L2 (measured faster than 48-column strips, whose
+// whole lines cost a third more halo loads).  The 64 lanes hold
 // 64 consecutive columns centred on the strip (the stencil needs 3 halo
 // columns on each side); x-neighbour values move between lanes through the LDS crossbar
 // (ds_bpermute); the raw populations of the last three rows sit in a per-wave
@@ -44,9 +44,8 @@ __shared__ double vlbm_pin_lds[8];
 // The LDS ring keeps lanes kRingLo .. kRingLo + kRingW - 1 only: stage C needs
 // the raw populations of the lanes whose post-collision populations stream into
 // owned columns, lanes halo-1 .. 64-halo, within that span for strips of at
-// most 50 columns (halo >= 7).  Twelve fewer lanes let eight FP64 wavefronts
-// per CU fit in LDS instead of six.
-constexpr int kRingLo = 6, kRingW = 52;
+// most 56 columns (halo >= 4).
+constexpr int kRingLo = 3, kRingW = 58;
 
 template <typename S, typename C, int EOS, int SENSOR>
 struct March {

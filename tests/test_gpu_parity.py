@@ -317,7 +317,8 @@ def test_tilings_agree_bitwise(monkeypatch, precision):
     reductions are maxima, exact in any order)."""
     W0, cfg, _ = riemann_case(200, 3)
     outs = []
-    for h, w, g in (("16", "48", "1"), ("37", "48", "2"), ("200", "32", "4"), ("23", "50", "3"), ("16", "16", "2")):
+    for h, w, g in (("16", "48", "1"), ("37", "48", "2"), ("200", "32", "4"), ("23", "50", "3"), ("16", "16", "2"),
+                    ("29", "56", "2")):
         monkeypatch.setenv("VLBM_SEG_H", h)
         monkeypatch.setenv("VLBM_STRIP_W", w)
         monkeypatch.setenv("VLBM_WPG", g)
