@@ -40,7 +40,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "d2q4_fp64_vortex1024_traffic.txt")
-KERNEL_SOURCES = ("paper_2609_10639_amd/csrc/vlbm_step2d.hip", "paper_2609_10639_amd/csrc/vlbm_common.hpp")
+KERNEL_SOURCES = ("paper_2609_10639_amd/csrc/vlbm_step2d.hip", "paper_2609_10639_amd/csrc/vlbm_common.hpp",
+                  "paper_2609_10639_amd/csrc/vlbm_api.cpp")
 
 
 def parse():
