@@ -25,6 +25,7 @@ struct KParams {
     int strip_w;              // D2Q4: output columns per wavefront (56; halo lanes (64 - strip_w)/2 a side)
     int nstrips, seg_h, nsegs; // D2Q4 tiling: strips of columns x segments of rows
     int wpg, ngroups;         // D2Q4 step: wavefronts (adjacent strips) per workgroup, strip groups
+    int deep;                 // D2Q4 FP64 step: two rows of loads in flight (one wavefront per SIMD)
 };
 
 // Per-launch control: where the clock and the reductions of the current state

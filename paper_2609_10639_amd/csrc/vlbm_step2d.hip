@@ -47,7 +47,7 @@ __shared__ double vlbm_pin_lds[8];
 // most 56 columns (halo >= 4).
 constexpr int kRingLo = 3, kRingW = 58;
 
-template <typename S, typename C, int EOS, int SENSOR>
+template <typename S, typename C, int EOS, int SENSOR, int DEPTH_>
 struct March {
     // uniform
     const KParams& P;
@@ -69,10 +69,13 @@ struct March {
     C Ss[3], Sth[3];           // S_x[s], S_x[theta]
     C yprev[4], wpend[4];      // f*_{+y} of the last collided row, pending moments of the row below
     // Rows in flight: with DEPTH 1 buf[0] holds the loads of row R+1 while row R
-    // is processed; with DEPTH 2 (FP32 storage: registers to spare) three buffers
-    // rotate with the unrolled phase, row R in buf[PH] and the loads of rows R+1
-    // and R+2 in the other two, so twice the bytes are in flight per wavefront.
-    static constexpr int DEPTH = sizeof(S) == 4 ? 2 : 1;
+    // is processed; with DEPTH 2 three buffers rotate with the unrolled phase,
+    // row R in buf[PH] and the loads of rows R+1 and R+2 in the other two, so
+    // twice the bytes are in flight per wavefront.  FP32 storage always has the
+    // registers for it; with FP64 storage it costs the second wavefront per SIMD
+    // (256 VGPRs and 18 AGPRs), which pays only on grids too small to fill the
+    // second one anyway.
+    static constexpr int DEPTH = DEPTH_;
     S buf[DEPTH == 2 ? 3 : 1][16];
     // reductions of the new state: maxima, and the admissibility witnesses
     C red_s, red_M[4];
@@ -318,7 +321,7 @@ extern __shared__ __align__(16) unsigned char vlbm_step_lds[];
 // They march in step (one barrier per row), so the halo lines that
 // neighbouring strips both read are fetched from HBM once and served to the
 // second reader from the caches.
-template <typename S, typename C, int EOS, int SENSOR>
+template <typename S, typename C, int EOS, int SENSOR, int DEPTH>
 __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep St, const S* __restrict__ fin,
                                                    S* __restrict__ fout)
 {
@@ -341,7 +344,7 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
         __syncthreads();
     }
 
-    March<S, C, EOS, SENSOR> m{P, St};
+    March<S, C, EOS, SENSOR, DEPTH> m{P, St};
     m.in = make_planes(fin, (unsigned)P.plane);
     m.out = make_planes((const S*)fout, (unsigned)P.plane);
     m.ring = ring;
@@ -426,17 +429,17 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
 
 // ------------------------------------------------------------------ launchers
 
-template <typename S, typename C>
+template <typename S, typename C, int DEPTH>
 static hipError_t launch_t(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
 {
     const dim3 grid(p.ngroups * p.nsegs), block(64 * p.wpg);
     const size_t lds = (size_t)p.wpg * 3 * 16 * kRingW * sizeof(S);
     const S* in = (const S*)fin;
     S* out = (S*)fout;
-#define VLBM_CASE(E, SN)                                                                       \
-    if (p.eos == E && p.sensor == SN) {                                                        \
-        hipLaunchKernelGGL((k_step_d2q4<S, C, E, SN>), grid, block, lds, st, p, s, in, out); \
-        return hipGetLastError();                                                              \
+#define VLBM_CASE(E, SN)                                                                              \
+    if (p.eos == E && p.sensor == SN) {                                                               \
+        hipLaunchKernelGGL((k_step_d2q4<S, C, E, SN, DEPTH>), grid, block, lds, st, p, s, in, out); \
+        return hipGetLastError();                                                                     \
     }
     VLBM_CASE(0, 0) VLBM_CASE(0, 1) VLBM_CASE(0, 2) VLBM_CASE(1, 0) VLBM_CASE(1, 1) VLBM_CASE(1, 2)
 #undef VLBM_CASE
@@ -446,9 +449,10 @@ static hipError_t launch_t(const KParams& p, const KStep& s, const void* fin, vo
 hipError_t launch_step_d2q4(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st)
 {
     switch (prec) {
-    case PREC_FP64: return launch_t<double, double>(p, s, fin, fout, st);
-    case PREC_FP32: return launch_t<float, float>(p, s, fin, fout, st);
-    case PREC_FP32_MIXED: return launch_t<float, double>(p, s, fin, fout, st);
+    case PREC_FP64:
+        return p.deep ? launch_t<double, double, 2>(p, s, fin, fout, st) : launch_t<double, double, 1>(p, s, fin, fout, st);
+    case PREC_FP32: return launch_t<float, float, 2>(p, s, fin, fout, st);
+    case PREC_FP32_MIXED: return launch_t<float, double, 2>(p, s, fin, fout, st);
     }
     return hipErrorInvalidValue;
 }
@@ -460,9 +464,12 @@ int step_d2q4_blocks_per_cu(const KParams& p, int prec)
     const int bs = 64 * p.wpg;
     const size_t l8 = (size_t)p.wpg * 3 * 16 * kRingW * 8, l4 = l8 / 2;
     switch (prec) {
-    case PREC_FP64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, double, 0, 2>, bs, l8); break;
-    case PREC_FP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, float, 0, 2>, bs, l4); break;
-    case PREC_FP32_MIXED: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, double, 0, 2>, bs, l4); break;
+    case PREC_FP64:
+        e = p.deep ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, double, 0, 2, 2>, bs, l8)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, double, 0, 2, 1>, bs, l8);
+        break;
+    case PREC_FP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, float, 0, 2, 2>, bs, l4); break;
+    case PREC_FP32_MIXED: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, double, 0, 2, 2>, bs, l4); break;
     }
     return e == hipSuccess ? nb : 0;
 }

@@ -312,16 +312,18 @@ def test_conservation_periodic(precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_mixed"])
 def test_tilings_agree_bitwise(monkeypatch, precision):
-    """Segment height, strip width and wavefronts per workgroup change only
-    which wavefront computes a cell: the populations agree bit for bit (the
-    reductions are maxima, exact in any order)."""
+    """Segment height, strip width, wavefronts per workgroup and rows of loads
+    in flight change only which wavefront computes a cell, or when: the
+    populations agree bit for bit (the reductions are maxima, exact in any
+    order)."""
     W0, cfg, _ = riemann_case(200, 3)
     outs = []
-    for h, w, g in (("16", "48", "1"), ("37", "48", "2"), ("200", "32", "4"), ("23", "50", "3"), ("16", "16", "2"),
-                    ("29", "56", "2")):
+    for h, w, g, d in (("16", "48", "1", "0"), ("37", "48", "2", "1"), ("200", "32", "4", "0"),
+                       ("23", "50", "3", "1"), ("16", "16", "2", "0"), ("29", "56", "2", "0"), ("29", "56", "1", "1")):
         monkeypatch.setenv("VLBM_SEG_H", h)
         monkeypatch.setenv("VLBM_STRIP_W", w)
         monkeypatch.setenv("VLBM_WPG", g)
+        monkeypatch.setenv("VLBM_DEEP", d)   # FP64: one or two rows of loads in flight
         s = _solver(cfg, precision)
         s.init(W0)
         s.step(30)
