@@ -103,7 +103,14 @@ int choose_seg_h(const KParams& p, int prec)
     const long long resident = (long long)cus * per_cu;   // workgroups resident at once
     long long nsegs = std::max(1LL, resident / p.ngroups);
     int h = (int)((p.ny + nsegs - 1) / nsegs);
-    h = std::max(h, 16);
+    // at least 10 rows: shorter segments spend more on their 6 halo rows than
+    // the extra wavefronts win (measured on MI355X at 512^2 and 1024^2, where
+    // 10-11 rows beat 16 by 9-20 % and 8 rows lose again).  FP64 frozen-speed
+    // contexts keep 16: the adjoint rollout replays them beside the FP64 adjoint
+    // march, which then finds free slots (end to end 3.4 -> 3.1 at 1024^2).
+    int hmin = prec == PREC_FP64 && p.retarget_every == 0 ? 16 : 10;
+    if (const char* env = getenv("VLBM_SEG_MIN")) hmin = std::max(1, atoi(env));
+    h = std::max(h, hmin);
     return std::min(h, p.ny);
 }
 
