@@ -51,7 +51,8 @@ struct AdjMarch {
     int nx, ny, y0, y1, Rb, Re;
     long long ncell;
     bool clo, chi;              // clamped y-low / y-high boundaries
-    int lane, lnb, rnb, X;
+    int lane, X;
+    bool kl, kr;       // the left / right neighbour is the cell itself (clamped edge)
     unsigned colx;
     bool owner, atL, atR;       // atL / atR: the clamped first / last column
 
@@ -80,13 +81,13 @@ struct AdjMarch {
     // transposed central difference along x: sum_x a(x) ([nb(x,+1)=z] - [nb(x,-1)=z])
     __device__ __forceinline__ C tdiff_x(C a) const
     {
-        const C l = shfl(a, lane > 0 ? lane - 1 : 0), r = shfl(a, lane < 63 ? lane + 1 : 63);
+        const C l = from_left(a, false), r = from_right(a, false);
         return (atL ? -a : l) + (atR ? a : -r);
     }
     // transposed (1/4, 1/2, 1/4) filter along x
     __device__ __forceinline__ C tbox_x(C a) const
     {
-        const C l = shfl(a, lane > 0 ? lane - 1 : 0), r = shfl(a, lane < 63 ? lane + 1 : 63);
+        const C l = from_left(a, false), r = from_right(a, false);
         return (C)0.25 * (atL ? a : l) + (C)0.5 * a + (C)0.25 * (atR ? a : r);
     }
 
@@ -124,12 +125,16 @@ struct AdjMarch {
                 const double cidx = (double)R * (double)nx + (double)X;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
+                    // selects, not branches: a branchy update let the optimiser
+                    // keep one of these in scratch memory
                     const C vx = fabs(qx[k]), vy = fabs(qy[k]);
-                    if (vx > amax[k]) { amax[k] = vx; aidx[k] = cidx; }
-                    if (vy > amax[k] || (vy == amax[k] && (double)ncell + cidx < aidx[k])) {
-                        amax[k] = vy;
-                        aidx[k] = (double)ncell + cidx;
-                    }
+                    const bool tx = vx > amax[k];
+                    amax[k] = tx ? vx : amax[k];
+                    aidx[k] = tx ? cidx : aidx[k];
+                    const double iy = (double)ncell + cidx;
+                    const bool ty = vy > amax[k] || (vy == amax[k] && iy < aidx[k]);
+                    amax[k] = ty ? vy : amax[k];
+                    aidx[k] = ty ? iy : aidx[k];
                 }
             }
             if constexpr (SENSOR != 0) {
@@ -142,8 +147,8 @@ struct AdjMarch {
                     const C gxm = (C)2 * (w4 - qx[k] * inv2c - fv[4 + k]);
                     const C gyy = (C)2 * (w4 + qy[k] * inv2c - fv[8 + k]);
                     const C gym = (C)2 * (w4 - qy[k] * inv2c - fv[12 + k]);
-                    const C lpr = shfl(lv[k], lane < 63 ? lane + 1 : 63);
-                    const C lml = shfl(lv[4 + k], lane > 0 ? lane - 1 : 0);
+                    const C lpr = from_right(lv[k], false);
+                    const C lml = from_left(lv[4 + k], false);
                     const C lsxp = (atR ? (C)0 : lpr) + (atL ? lv[k] : (C)0);
                     const C lsxm = (atL ? (C)0 : lml) + (atR ? lv[4 + k] : (C)0);
                     bx += gxp * lsxp + gxm * lsxm;
@@ -170,7 +175,7 @@ struct AdjMarch {
                 for (int k = 0; k < 4; ++k) {
                     const C hq = (C)0.5 * qy[k];
                     J1[k] += hq;
-                    J0[k] += (C)0.5 * (shfl(qx[k], rnb) - shfl(qx[k], lnb));
+                    J0[k] += (C)0.5 * (from_right(qx[k], kr) - from_left(qx[k], kl));
                     Jn[k] = -hq;
                     if (clo && R == 0) J0[k] -= hq;
                     if (chi && R == ny - 1) J0[k] += hq;
@@ -179,8 +184,8 @@ struct AdjMarch {
                     const C hx = ux * inv2dx, hy = uy * inv2dx;
                     D1 += hy;
                     V1 -= hx;
-                    D0 += (shfl(ux, rnb) - shfl(ux, lnb)) * inv2dx;
-                    V0 += (shfl(uy, rnb) - shfl(uy, lnb)) * inv2dx;
+                    D0 += (from_right(ux, kr) - from_left(ux, kl)) * inv2dx;
+                    V0 += (from_right(uy, kr) - from_left(uy, kl)) * inv2dx;
                     Dn = -hy;
                     Vn = hx;
                     if (clo && R == 0) { D0 -= hy; V0 += hx; }
@@ -206,11 +211,11 @@ struct AdjMarch {
                 hr[hs][4][lane] = D1;
                 hr[hs][5][lane] = V1;
                 hr[hs][6][lane] = s1;
-                Ss1 = (C)0.25 * shfl(s1, lnb) + (C)0.5 * s1 + (C)0.25 * shfl(s1, rnb);
+                Ss1 = (C)0.25 * from_left(s1, kl) + (C)0.5 * s1 + (C)0.25 * from_right(s1, kr);
                 if constexpr (SENSOR == 2) {
                     const C d2 = D1 * D1;
                     const C th = d2 / (fma(V1, V1, d2) + eps);
-                    Th1 = (C)0.25 * shfl(th, lnb) + (C)0.5 * th + (C)0.25 * shfl(th, rnb);
+                    Th1 = (C)0.25 * from_left(th, kl) + (C)0.5 * th + (C)0.25 * from_right(th, kr);
                 }
                 hr[hs][7][lane] = Ss1;
                 hr[hs][8][lane] = Th1;
@@ -314,7 +319,7 @@ struct AdjMarch {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const C lp = (C)bload(lin, k, offo, S()), lm = (C)bload(lin, 4 + k, offo, S());
-                const C lpr = shfl(lp, lane < 63 ? lane + 1 : 63), lml = shfl(lm, lane > 0 ? lane - 1 : 0);
+                const C lpr = from_right(lp, false), lml = from_left(lm, false);
                 ls[k] = (atR ? (C)0 : lpr) + (atL ? lp : (C)0);
                 ls[4 + k] = (atL ? (C)0 : lml) + (atR ? lm : (C)0);
                 const C lyu = (C)bload(lin, 8 + k, offu, S()), lyd = (C)bload(lin, 12 + k, offd, S());
@@ -414,8 +419,8 @@ __global__ void __launch_bounds__(64) k_adj_march(const KParams P, const S* __re
     m.colx = (unsigned)cx;
     m.atL = P.bc[0] == 1 && m.X == 0;
     m.atR = P.bc[1] == 1 && m.X == m.nx - 1;
-    m.lnb = m.atL ? m.lane : max(m.lane - 1, 0);
-    m.rnb = m.atR ? m.lane : min(m.lane + 1, 63);
+    m.kl = m.atL;
+    m.kr = m.atR;
     m.owner = m.lane >= halo && m.lane < halo + P.strip_w && m.X < m.nx;
     m.clo = P.bc[2] == 1;
     m.chi = P.bc[3] == 1;

@@ -8,8 +8,8 @@
 // and the parts merge in L2 (measured faster than 48-column strips, whose
 // whole lines cost a third more halo loads).  The 64 lanes hold
 // 64 consecutive columns centred on the strip (the stencil needs 3 halo
-// columns on each side); x-neighbour values move between lanes through the LDS crossbar
-// (ds_bpermute); the raw populations of the last three rows sit in a per-wave
+// columns on each side); x-neighbour values move between lanes by DPP
+// wavefront shifts or through the LDS crossbar; the raw populations of the last three rows sit in a per-wave
 // LDS ring; the per-row partial sums that later rows complete sit in
 // registers.  The march is unrolled by three so that every row slot (LDS ring
 // and register histories alike) is a compile-time index.
@@ -60,7 +60,9 @@ struct March {
     int nx, ny, y0, y1, Rb, Re;
     bool clo, chi;
     // per lane
-    int lane, lnb, rnb, X;
+    int lane, X;
+    int lnb, rnb;      // lanes of the x-1 / x+1 neighbours (the own lane at a clamped edge)
+    bool kl, kr;       // clamped x edge: the left / right neighbour is the cell itself
     int rl;            // this lane's ring column (clamped; lanes outside the span never write)
     unsigned colx;     // column loaded by this lane
     bool owner;
@@ -77,6 +79,23 @@ struct March {
     // second one anyway.
     static constexpr int DEPTH = DEPTH_;
     S buf[DEPTH == 2 ? 3 : 1][16];
+    // x-neighbour values: DPP wavefront shifts (VALU) where a wavefront runs
+    // alone on its SIMD and the march is latency-bound (two rows in flight),
+    // the LDS crossbar (ds_bpermute) where two FP64 wavefronts share the VALU
+    // (measured: 1024^2 FP64 +4.5 % with DPP, 4096^2 FP64 -1.8 %)
+    static constexpr bool kDpp = DEPTH == 2;
+    template <typename T>
+    __device__ __forceinline__ T left(T v) const
+    {
+        if constexpr (kDpp) return from_left(v, kl);
+        else return shfl(v, lnb);
+    }
+    template <typename T>
+    __device__ __forceinline__ T right(T v) const
+    {
+        if constexpr (kDpp) return from_right(v, kr);
+        else return shfl(v, rnb);
+    }
     // reductions of the new state: maxima, and the admissibility witnesses
     C red_s, red_M[4];
     int ebits;                 // admissibility of the new state: ERR_NONHYP | ERR_NONFINITE
@@ -176,8 +195,8 @@ struct March {
                     const C a = (C)0.25 * W[k], m = mu * (Sx[k] - Sy[k]);
                     const C cx = fma(nu, Dx[k], tau * qx[k]), cy = fma(nu, Dy[k], tau * qy[k]);
                     const C ap = a + m, am = a - m;
-                    gx[k] = shfl(ap + cx, lnb);       // +x population arriving from x-1
-                    gx[4 + k] = shfl(ap - cx, rnb);   // -x population arriving from x+1
+                    gx[k] = left(ap + cx);       // +x population arriving from x-1
+                    gx[4 + k] = right(ap - cx);   // -x population arriving from x+1
                     fyp[k] = am + cy;
                     fym[k] = am - cy;
                 }
@@ -263,7 +282,7 @@ struct March {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     J[cR1][k] += hq[k];                                             // completes row R-1
-                    J[cR][k] += (C)0.5 * (shfl(qx[k], rnb) - shfl(qx[k], lnb));      // x-part of row R
+                    J[cR][k] += (C)0.5 * (right(qx[k]) - left(qx[k]));      // x-part of row R
                     J[cR2][k] = -hq[k];                                             // starts row R+1
                 }
                 C hx = 0, hy = 0;
@@ -272,8 +291,8 @@ struct March {
                     hy = uy * inv2dx;
                     Dl[cR1] += hy;
                     Vo[cR1] -= hx;
-                    Dl[cR] += (shfl(ux, rnb) - shfl(ux, lnb)) * inv2dx;
-                    Vo[cR] += (shfl(uy, rnb) - shfl(uy, lnb)) * inv2dx;
+                    Dl[cR] += (right(ux) - left(ux)) * inv2dx;
+                    Vo[cR] += (right(uy) - left(uy)) * inv2dx;
                     Dl[cR2] = -hy;
                     Vo[cR2] = hx;
                 }
@@ -303,11 +322,11 @@ struct March {
                     acc = fma(sh, sh, acc);
                 }
                 const C sq = fast_sqrt(acc * (C)0.25);
-                Ss[cR1] = (C)0.25 * shfl(sq, lnb) + (C)0.5 * sq + (C)0.25 * shfl(sq, rnb);
+                Ss[cR1] = (C)0.25 * left(sq) + (C)0.5 * sq + (C)0.25 * right(sq);
                 if constexpr (SENSOR == 2) {
                     const C d2 = Dl[cR1] * Dl[cR1];
                     const C th = d2 * fast_rcp(fma(Vo[cR1], Vo[cR1], d2) + (C)P.eps_theta);
-                    Sth[cR1] = (C)0.25 * shfl(th, lnb) + (C)0.5 * th + (C)0.25 * shfl(th, rnb);
+                    Sth[cR1] = (C)0.25 * left(th) + (C)0.5 * th + (C)0.25 * right(th);
                 }
             }
         }
@@ -372,13 +391,10 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
     if (m.X < 0) cx = P.bc[0] == 0 ? wrap_index(m.X, m.nx) : 0;
     else if (m.X >= m.nx) cx = P.bc[1] == 0 ? wrap_index(m.X, m.nx) : m.nx - 1;
     m.colx = (unsigned)cx;
-    m.lnb = m.lane - 1;
-    m.rnb = m.lane + 1;
-    if (P.bc[0] != 0 && m.X == 0) m.lnb = m.lane;   // outflow and pinned edges clamp the stencils
-    if (P.bc[1] != 0 && m.X == m.nx - 1) m.rnb = m.lane;
-
-    m.lnb = max(m.lnb, 0);
-    m.rnb = min(m.rnb, 63);
+    m.kl = P.bc[0] != 0 && m.X == 0;   // outflow and pinned edges clamp the stencils
+    m.kr = P.bc[1] != 0 && m.X == m.nx - 1;
+    m.lnb = m.kl ? m.lane : max(m.lane - 1, 0);
+    m.rnb = m.kr ? m.lane : min(m.lane + 1, 63);
     m.owner = m.lane >= halo && m.lane < halo + P.strip_w && m.X < m.nx && strip < P.nstrips;
     m.clo = P.bc[2] == 1;
     m.chi = P.bc[3] == 1;
