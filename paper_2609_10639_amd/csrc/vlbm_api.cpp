@@ -287,15 +287,16 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
         if (v >= 8 && v <= 56 && v % 2 == 0) p.strip_w = v;   // the step's LDS ring covers halos >= 4
     }
     p.nstrips = (p.nx + p.strip_w - 1) / p.strip_w;
-    // FP64 below 2M cells: two rows of loads in flight per wavefront at one
+    // FP64 below 1.5M cells: two rows of loads in flight per wavefront at one
     // wavefront per SIMD, where too few strips x segments exist to fill a second
-    // (measured on MI355X: 512^2 and 1024^2 3-4 % faster, 1536^2 3 % slower,
-    // 2048^2 7 % and 4096^2 14 % slower).  Not for frozen-speed contexts: they
-    // serve the adjoint rollout, whose replay runs beside the FP64 adjoint march,
-    // and a wavefront of 274 registers cannot share a SIMD with one of its (248).
+    // (measured on MI355X: 512^2 and 1024^2 3-8 % faster; 1280^2 and 1536^2
+    // 1.5 % slower, 2048^2 5 %, 4096^2 14 %).  Not for frozen-speed contexts:
+    // they serve the adjoint rollout, whose replay runs beside the FP64 adjoint
+    // march, and a wavefront holding more than half of a SIMD's registers
+    // (255 VGPRs and 14 AGPRs) cannot share it with one of the march's (248).
     const long long cells = p.nx * (long long)p.ny;
     const bool small = cells < (1LL << 22);
-    p.deep = ctx->prec == PREC_FP64 && cells < (1LL << 21) && cfg->retarget_every != 0;
+    p.deep = ctx->prec == PREC_FP64 && cells < 3 * (1LL << 19) && cfg->retarget_every != 0;
     if (const char* env = getenv("VLBM_DEEP")) p.deep = ctx->prec == PREC_FP64 && atoi(env) != 0;
     // adjacent strips per workgroup (measured on MI355X): 2 FP64 wavefronts
     // (22 KB of LDS ring each), 1 with two rows in flight; with FP32 storage 4
