@@ -1,9 +1,13 @@
 // Fused D1Q2 VLBM time step for gfx950 (arXiv 2609.10639, Sec. III).
 //
-// A 256-thread workgroup processes tiles of 256 consecutive cells (grid-stride
-// over the tiles, at most 1024 workgroups with FP64 storage and 4096 with FP32
-// storage, whose tiles carry half the bytes: measured best on MI355X).  It stages the 262 cells of a tile
-// plus a 3-cell halo in LDS and runs the step in four barrier-separated phases:
+// A 256-thread workgroup processes tiles of consecutive cells (grid-stride over
+// the tiles): 256 cells with FP64 arithmetic, 512 with FP32 arithmetic, whose
+// cells carry half the bytes, so that the fixed cost of a tile (four barriers,
+// the halo) is spread over as many bytes (FP32: +4 %).  At most 1024
+// workgroups with FP64 storage, 4096 with FP32 storage and FP64 arithmetic,
+// 2048 with FP32 (measured best on MI355X).  It stages the
+// cells of a tile plus a 3-cell halo in LDS and runs the step in four
+// barrier-separated phases:
 //   A  load the 6 populations (SoA planes, coalesced), reproject to the new
 //      link speed (Sec. III.E, D = 1 form of Eq. 40), flux Q(W) (Eq. 10);
 //   B  normalised flux-divergence activity s (Eqs. 28-31);
@@ -15,16 +19,18 @@
 
 namespace vlbm {
 
-constexpr int kTile1 = 256;
+constexpr int kBlock1 = 256;   // threads per workgroup
 constexpr int kHalo1 = 3;
-constexpr int kSlots1 = kTile1 + 2 * kHalo1;
 constexpr int kGrid1 = 1024;   // blocks per launch, FP64 storage (4 per CU); each strides over the tiles
-constexpr int kGrid1F = 4096;  // the same with FP32 storage (16 per CU)
+constexpr int kGrid1F = 4096;  // the same with FP32 storage (16 per CU), for tiles of 256 cells
 
-template <typename ST, typename T, int EOS, int SENSOR>
-__global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep S, const ST* __restrict__ fin,
-                                                   ST* __restrict__ fout)
+template <typename ST, typename T, int EOS, int SENSOR, int TILE>
+__global__ void __launch_bounds__(kBlock1) k_step_d1q2(const KParams P, const KStep S, const ST* __restrict__ fin,
+                                                       ST* __restrict__ fout)
 {
+    constexpr int kSlots1 = TILE + 2 * kHalo1;
+    constexpr int NS = (kSlots1 + kBlock1 - 1) / kBlock1;   // slot sets per thread, the last one partial
+    static_assert(TILE % kBlock1 == 0, "whole output cells per thread");
     __shared__ T sf[6][kSlots1];   // reprojected populations, plane i*3+k (arithmetic type)
     __shared__ T sq[3][kSlots1];   // flux Q_k
     __shared__ T sa[kSlots1];      // activity s
@@ -53,58 +59,61 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
     // replaces the population streaming in across it by its ghost's equilibrium
     const bool cl = P.bc[0] != 0, ch = P.bc[1] != 0;
     const bool pl = P.bc[0] == 2, ph = P.bc[1] == 2;
-    const int ntiles = (nx + kTile1 - 1) / kTile1;
+    const int ntiles = (nx + TILE - 1) / TILE;
 
     // reductions of the new state over every tile this block visits
     double red_s = 0.0, red_M[3] = {0.0, 0.0, 0.0};
     int errbits = 0;
 
-    // slot s of tile t holds cell X = t kTile1 - 3 + s; neighbours follow the boundary rule
+    // slot s of tile t holds cell X = t TILE - 3 + s; neighbours follow the boundary rule
     auto cell_of = [&](int X) {
         if (X < 0) return cl ? 0 : wrap_index(X, nx);
         if (X >= nx) return ch ? nx - 1 : wrap_index(X, nx);
         return X;
     };
-    // Each thread owns slot threadIdx.x and, for the first 2 kHalo1 threads, slot
-    // threadIdx.x + kTile1.  With FP32 storage the populations of its slots of
-    // the next tile are loaded while the current tile is processed (measured
-    // +8 %; with FP64 storage the extra registers cost more than they hide, -4 %).
-    // The loads are unconditional (past the last tile the last tile is re-read,
-    // in bounds; a thread without a second slot re-reads its first), so they
-    // never merge through copies that wait at once.
+    // Each thread owns slots threadIdx.x + h kBlock1 (h < NS; the last set only
+    // for the first kSlots1 - (NS - 1) kBlock1 threads).  With FP32 storage the
+    // populations of its slots of the next tile are loaded while the current
+    // tile is processed (measured +8 %; with FP64 storage the extra registers
+    // cost more than they hide, -4 %).  The loads are unconditional (past the
+    // last tile the last tile is re-read, in bounds; a thread without a slot in
+    // the last set re-reads its first), so they never merge through copies that
+    // wait at once.
     constexpr bool kAhead = sizeof(ST) == 4;
-    const bool two = threadIdx.x + kTile1 < kSlots1;
-    const int s2 = two ? threadIdx.x + kTile1 : threadIdx.x;
-    ST pa[6], pb[6];
+    const bool two = threadIdx.x + (NS - 1) * kBlock1 < kSlots1;   // owns a slot of the last set
+    ST pre[NS][6];
     auto load_slots = [&](int t) {
-        const int ca = cell_of(t * kTile1 - kHalo1 + (int)threadIdx.x), cb = cell_of(t * kTile1 - kHalo1 + s2);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) pa[j] = fin[j * plane + ca];
-        if (kAhead || two)
+        for (int h = 0; h < NS; ++h) {
+            const int sl = threadIdx.x + h * kBlock1;
+            const bool full = h < NS - 1;
+            if (full || kAhead || two) {
+                const int c = cell_of(t * TILE - kHalo1 + (full || two ? sl : (int)threadIdx.x));
 #pragma unroll
-            for (int j = 0; j < 6; ++j) pb[j] = fin[j * plane + cb];
+                for (int j = 0; j < 6; ++j) pre[h][j] = fin[j * plane + c];
+            }
+        }
     };
     if (kAhead && (int)blockIdx.x < ntiles) load_slots(blockIdx.x);
 
-    // grid-stride over tiles of kTile1 cells: few blocks, one set of atomics each
+    // grid-stride over tiles of TILE cells: few blocks, one set of atomics each
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int x0 = tile * kTile1;
+        const int x0 = tile * TILE;
         auto left_of = [&](int s) { return (cl && x0 - kHalo1 + s == 0) ? s : s - 1; };
         auto right_of = [&](int s) { return (ch && x0 - kHalo1 + s == nx - 1) ? s : s + 1; };
         if (!kAhead) load_slots(tile);
-        ST cur[2][6];
+        ST cur[NS][6];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            cur[0][j] = pa[j];
-            cur[1][j] = pb[j];
-        }
+        for (int h = 0; h < NS; ++h)
+#pragma unroll
+            for (int j = 0; j < 6; ++j) cur[h][j] = pre[h][j];
         if (kAhead) load_slots(min(tile + (int)gridDim.x, ntiles - 1));
 
         // ---- A
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (h == 1 && !two) break;
-            const int s = h == 0 ? (int)threadIdx.x : s2;
+        for (int h = 0; h < NS; ++h) {
+            if (h == NS - 1 && !two) break;
+            const int s = threadIdx.x + h * kBlock1;
             T f[6];
 #pragma unroll
             for (int j = 0; j < 6; ++j) f[j] = (T)cur[h][j];
@@ -130,7 +139,7 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
         __syncthreads();
         // ---- B
         if constexpr (SENSOR != 0) {
-            for (int s = threadIdx.x + 1; s < kSlots1 - 1; s += kTile1) {
+            for (int s = threadIdx.x + 1; s < kSlots1 - 1; s += kBlock1) {
                 const int sl = left_of(s), sr = right_of(s);
                 T acc = 0, j0 = 0;
 #pragma unroll
@@ -146,7 +155,7 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
             __syncthreads();
         }
         // ---- C
-        for (int s = threadIdx.x + 2; s < kSlots1 - 2; s += kTile1) {
+        for (int s = threadIdx.x + 2; s < kSlots1 - 2; s += kBlock1) {
             T beta = (T)P.beta_const;
             if constexpr (SENSOR != 0) {
                 const T sbar = (T)0.25 * sa[left_of(s)] + (T)0.5 * sa[s] + (T)0.25 * sa[right_of(s)];
@@ -156,7 +165,7 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
             }
             const int X = x0 - kHalo1 + s;
             if (S.probe) {
-                if (s >= kHalo1 && s < kHalo1 + kTile1 && X < nx) S.beta_out[X] = (double)beta;
+                if (s >= kHalo1 && s < kHalo1 + TILE && X < nx) S.beta_out[X] = (double)beta;
                 continue;
             }
             const T tb = (T)2 * beta;
@@ -170,9 +179,11 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
         }
         __syncthreads();
         // ---- D
-        if (!S.probe) {
-            const int s = kHalo1 + threadIdx.x;
-            const int X = x0 + threadIdx.x;
+#pragma unroll
+        for (int h = 0; h < TILE / kBlock1; ++h) {
+            if (S.probe) break;
+            const int s = kHalo1 + threadIdx.x + h * kBlock1;
+            const int X = x0 + threadIdx.x + h * kBlock1;
             if (X < nx) {
                 const int sl = left_of(s), sr = right_of(s);
                 T gn[6];
@@ -204,37 +215,49 @@ __global__ void __launch_bounds__(256) k_step_d1q2(const KParams P, const KStep 
         }
         __syncthreads();   // the next tile overwrites sf, sq, sa and sg
     }
-    if (!S.probe) block_publish<kTile1 / 64>(S, red_s, red_M, 3, errbits);
+    if (!S.probe) block_publish<kBlock1 / 64>(S, red_s, red_M, 3, errbits);
 }
 
-template <typename ST, typename T>
+template <typename ST, typename T, int TILE>
 static hipError_t launch_t(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
 {
-    const int ntiles = (p.nx + kTile1 - 1) / kTile1;
-    int gmax = sizeof(ST) == 4 ? kGrid1F : kGrid1;
+    const int ntiles = (p.nx + TILE - 1) / TILE;
+    int gmax = sizeof(ST) == 4 ? kGrid1F * 256 / TILE : kGrid1;   // FP32 tiles of 512: 2048 blocks
     if (const char* env = getenv("VLBM_D1_GRID")) {   // tuning override
         const int v = atoi(env);
         if (v >= 64 && v <= 65536) gmax = v;
     }
-    const dim3 grid(ntiles < gmax ? ntiles : gmax), block(kTile1);
+    const dim3 grid(ntiles < gmax ? ntiles : gmax), block(kBlock1);
     const ST* in = (const ST*)fin;
     ST* out = (ST*)fout;
-#define VLBM_CASE(E, SN)                                                                      \
-    if (p.eos == E && p.sensor == SN) {                                                       \
-        hipLaunchKernelGGL((k_step_d1q2<ST, T, E, SN>), grid, block, 0, st, p, s, in, out); \
-        return hipGetLastError();                                                             \
+#define VLBM_CASE(E, SN)                                                                            \
+    if (p.eos == E && p.sensor == SN) {                                                             \
+        hipLaunchKernelGGL((k_step_d1q2<ST, T, E, SN, TILE>), grid, block, 0, st, p, s, in, out); \
+        return hipGetLastError();                                                                   \
     }
     VLBM_CASE(0, 0) VLBM_CASE(0, 1) VLBM_CASE(1, 0) VLBM_CASE(1, 1)
 #undef VLBM_CASE
     return hipErrorInvalidValue;
 }
 
+// cells per tile: 512 with FP32 arithmetic, 256 with FP64 (VLBM_D1_TILE overrides, for tuning)
+template <typename ST, typename T>
+static hipError_t launch_tiled(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
+{
+    int tile = sizeof(T) == 4 ? 512 : 256;
+    if (const char* env = getenv("VLBM_D1_TILE")) {
+        const int v = atoi(env);
+        if (v == 256 || v == 512) tile = v;
+    }
+    return tile == 512 ? launch_t<ST, T, 512>(p, s, fin, fout, st) : launch_t<ST, T, 256>(p, s, fin, fout, st);
+}
+
 hipError_t launch_step_d1q2(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st)
 {
     switch (prec) {
-    case PREC_FP64: return launch_t<double, double>(p, s, fin, fout, st);
-    case PREC_FP32: return launch_t<float, float>(p, s, fin, fout, st);
-    case PREC_FP32_MIXED: return launch_t<float, double>(p, s, fin, fout, st);
+    case PREC_FP64: return launch_tiled<double, double>(p, s, fin, fout, st);
+    case PREC_FP32: return launch_tiled<float, float>(p, s, fin, fout, st);
+    case PREC_FP32_MIXED: return launch_tiled<float, double>(p, s, fin, fout, st);
     }
     return hipErrorInvalidValue;
 }
