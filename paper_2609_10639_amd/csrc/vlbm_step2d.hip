@@ -1,21 +1,21 @@
 // Fused D2Q4 VLBM time step for gfx950 (arXiv 2609.10639, Sec. III).
 //
 // One wavefront owns a strip of output columns and marches up a segment of
-// rows.  The strip is 56 columns, with 4 halo lanes on each side: the
-// stencil chain needs 3 halo columns and streaming one more.  56 columns are
-// three and a half 128-byte lines in FP64 and one and three quarters in FP32;
-// the strips that share a line write their parts of it in the same row sweep
-// and the parts merge in L2 (measured faster than 48-column strips, whose
-// whole lines cost a third more halo loads).  The 64 lanes hold
-// 64 consecutive columns centred on the strip (the stencil needs 3 halo
-// columns on each side); x-neighbour values move between lanes by DPP
-// wavefront shifts or through the LDS crossbar; the raw populations of the last three rows sit in a per-wave
-// LDS ring; the per-row partial sums that later rows complete sit in
-// registers.  The march is unrolled by three so that every row slot (LDS ring
-// and register histories alike) is a compile-time index.
+// rows.  The strip is 56 columns; the 64 lanes hold 64 consecutive columns
+// centred on it, 4 halo lanes on each side (the stencil chain needs 3 halo
+// columns and streaming one more).  56 columns are three and a half 128-byte
+// lines in FP64 and one and three quarters in FP32; the strips that share a
+// line write their parts of it in the same row sweep and the parts merge in L2
+// (measured faster than 48-column strips, whose whole lines cost a third more
+// halo loads).  x-neighbour values move between lanes by DPP wavefront shifts
+// or through the LDS crossbar; the raw populations of the last three rows sit
+// in a per-wave LDS ring; the per-row partial sums that later rows complete
+// sit in registers.  The march is unrolled by three so that every row slot
+// (LDS ring and register histories alike) is a compile-time index.
 //
 // Iteration R (front row R) runs, in this order:
-//   issue the global loads of row R (they stay in flight during stage C);
+//   issue the global loads of row R+DEPTH (DEPTH rows stay in flight: one with
+//               FP64 storage on large grids, else two);
 //   C  row R-3  y-pass of the box filter, beta (Eqs. 34-35), reprojection to
 //               the new link speed (Eqs. 38-40) of the populations read back
 //               from LDS, over-relaxation towards the vector equilibrium
