@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--big-grid", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline measurement only")
-    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=500)   # about 10 s of host time on 16 threads
     ap.add_argument("--only", default="", help="profiling aid: fp64 | fp32 | fp32_mixed | big64 | big32 | "
                                                 "riemann32 | d1q2_64 | d1q2_32 | adjoint32 | adjoint64 | copy")
     return ap.parse_args()
