@@ -260,22 +260,33 @@ def cpu_baseline(n, steps):
 
 
 def copy_bw(nbytes, steps, warmup):
-    """Plain device copy of `nbytes`: attainable bandwidth and the reference for
-    the hardware byte counters."""
+    """Plain device copies of `nbytes`: torch's copy_ and the library's probe
+    (16-byte non-temporal loads and stores): attainable bandwidth, and the
+    reference for the hardware byte counters (torch's copy)."""
     import torch
+    from paper_2609_10639_amd import _native
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(warmup):
-        dst.copy_(src)
-    e0, e1 = _events()
-    e0.record()
-    for _ in range(steps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": round(ms, 5),
-            "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        e0, e1 = _events()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        return {"ms": round(ms, 5), "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+    torch_copy = timed(lambda: dst.copy_(src))
+    dst.zero_()
+    probe = timed(lambda: _native.copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, stream))
+    ok = bool(torch.equal(src, dst))
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "torch_copy": torch_copy, "probe": probe,
+            "probe_copied_exactly": ok}
 
 
 # ------------------------------------------------------------------ main
@@ -347,6 +358,8 @@ def main():
                                             for p in ("fp64", "fp32")}}
         del W1
         out["adjoint"] = [adjoint_ratio("fp32"), adjoint_ratio("fp64")]
+        # context for the roofline fractions: a plain device copy of one 4096^2 FP64 population array
+        out["copy"] = copy_bw(16 * nb * nb * 8, 20, 3)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.grid, a.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -200,6 +200,16 @@ vlbm_status vlbm_raw_moments_adjoint(vlbm_ctx* ctx, const double* Wbar, void* la
 /* Message of the last failing call on this context (valid until the next call). */
 const char* vlbm_last_error(const vlbm_ctx* ctx);
 
+/* Measurement aid, not part of the method: copies `bytes` (a multiple of 16)
+ * from the device buffer src to the device buffer dst, which must not overlap,
+ * with a grid-stride kernel of 16-byte non-temporal loads and stores: the
+ * attainable-bandwidth reference that roofline fractions are read against.
+ * Stream-ordered on `stream` (a hipStream_t; NULL: the null stream), returns
+ * before the copy completes; the caller owns both buffers.  VLBM_EINVAL for a
+ * null pointer or a size that is not a multiple of 16, VLBM_EDEVICE if the
+ * launch fails. */
+vlbm_status vlbm_copy_probe(const void* src, void* dst, size_t bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -80,6 +80,7 @@ _SIGS = [
     ("vlbm_raw_moments", ctypes.c_int, [_P, _P, _P]),
     ("vlbm_raw_moments_adjoint", ctypes.c_int, [_P, _P, _P]),
     ("vlbm_last_error", ctypes.c_char_p, [_P]),
+    ("vlbm_copy_probe", ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
 ]
 EXPORTED = [name for name, _, _ in _SIGS]
 
@@ -104,3 +105,9 @@ def check(status, handle=None):
     if status != OK:
         msg = lib().vlbm_last_error(handle).decode() if handle else ""
         raise VlbmError(status, msg)
+
+
+def copy_probe(src, dst, nbytes, stream):
+    """vlbm_copy_probe: device-to-device copy of nbytes through the library's
+    bandwidth probe kernel (a measurement aid), stream-ordered."""
+    check(lib().vlbm_copy_probe(src, dst, nbytes, stream))

@@ -654,4 +654,10 @@ vlbm_status vlbm_raw_moments_adjoint(vlbm_ctx* ctx, const double* Wbar, void* la
 
 const char* vlbm_last_error(const vlbm_ctx* ctx) { return ctx ? ctx->msg.c_str() : "null context"; }
 
+vlbm_status vlbm_copy_probe(const void* src, void* dst, size_t bytes, void* stream)
+{
+    if (!src || !dst || bytes % 16 != 0) return VLBM_EINVAL;
+    return launch_copy_probe(src, dst, bytes, (hipStream_t)stream) == hipSuccess ? VLBM_OK : VLBM_EDEVICE;
+}
+
 }  // extern "C"
