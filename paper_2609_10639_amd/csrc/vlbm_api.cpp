@@ -222,6 +222,16 @@ bool check_config(const vlbm_config* c, std::string& why)
         return why = "bad sensor constants", false;
     if (c->precision != VLBM_FP64 && c->precision != VLBM_FP32 && c->precision != VLBM_FP32_MIXED)
         return why = "bad precision", false;
+    if (c->dim == 2) {
+        // the D2Q4 marches address four planes from one buffer resource with
+        // 32-bit offsets: 4 padded planes must fit in 4 GiB (2^27 cells in FP64,
+        // 2^28 with FP32 storage)
+        const long long plane = (c->nx * c->ny + 63) / 64 * 64;
+        const long long esize = c->precision == VLBM_FP64 ? 8 : 4;
+        if (4 * plane * esize > (1LL << 32))
+            return why = "grid too large for the D2Q4 kernels' 32-bit offsets (2^27 cells in FP64, 2^28 with FP32 storage)",
+                   false;
+    }
     return true;
 }
 

@@ -56,3 +56,28 @@ def test_config_struct_matches_header_layout(tmp_path):
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [getattr(_native.VlbmConfig, f).offset for f in fields] + [ctypes.sizeof(_native.VlbmConfig)]
     assert got == want, list(zip(fields + ["sizeof"], got, want))
+
+def _config(dim, nx, ny, precision):
+    from paper_2609_10639_amd import _native
+    c = _native.VlbmConfig()
+    c.dim, c.nx, c.ny, c.dx = dim, nx, ny, 1.0 / nx
+    c.eos, c.gamma, c.cfl, c.retarget_every = 0, 1.4, 0.45, 1
+    c.sensor, c.beta_const, c.beta_min, c.beta_max, c.c_sensor, c.eps_theta = 2, 1.0, 0.75, 1.0, 4.0, 1e-12
+    c.precision = precision
+    return c
+
+
+@pytest.mark.parametrize("nx,ny,precision", [(11586, 11586, 0), (16384, 8193, 0), (16384, 16385, 1),
+                                             (16384, 16385, 2), (1 << 20, 1 << 12, 1)])
+def test_grids_beyond_32bit_offsets_are_rejected(nx, ny, precision):
+    """The D2Q4 kernels address four population planes from one buffer
+    resource with 32-bit offsets; larger grids are refused by the
+    configuration check, before any device call."""
+    from paper_2609_10639_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        pytest.skip("libvlbm.so not built")
+    lib = _native.lib()
+    out = ctypes.c_void_p()
+    c = _config(2, nx, ny, precision)
+    assert lib.vlbm_create(ctypes.byref(c), ctypes.byref(out)) == _native.EINVAL
+    assert not out.value
