@@ -47,7 +47,9 @@ __shared__ double vlbm_pin_lds[8];
 // most 56 columns (halo >= 4).
 constexpr int kRingLo = 3, kRingW = 58;
 
-template <typename S, typename C, int EOS, int SENSOR, int DEPTH_>
+// XPER: both x edges periodic (no clamped column, no pinned ghost), so the
+// neighbour moves need no edge selects.
+template <typename S, typename C, int EOS, int SENSOR, int DEPTH_, bool XPER>
 struct March {
     // uniform
     const KParams& P;
@@ -87,13 +89,30 @@ struct March {
     template <typename T>
     __device__ __forceinline__ T left(T v) const
     {
-        if constexpr (kDpp) return from_left(v, kl);
+        if constexpr (kDpp && XPER) return dpp_move<kDppWaveShr1>(v);
+        else if constexpr (kDpp) return from_left(v, kl);
         else return shfl(v, lnb);
     }
     template <typename T>
     __device__ __forceinline__ T right(T v) const
     {
-        if constexpr (kDpp) return from_right(v, kr);
+        if constexpr (kDpp && XPER) return dpp_move<kDppWaveShl1>(v);
+        else if constexpr (kDpp) return from_right(v, kr);
+        else return shfl(v, rnb);
+    }
+    // the same for a value computed from the loaded column alone: the lane
+    // beyond a clamped edge loaded the edge column, so it already holds the
+    // clamped neighbour's value and no select is needed
+    template <typename T>
+    __device__ __forceinline__ T left_col(T v) const
+    {
+        if constexpr (kDpp) return dpp_move<kDppWaveShr1>(v);
+        else return shfl(v, lnb);
+    }
+    template <typename T>
+    __device__ __forceinline__ T right_col(T v) const
+    {
+        if constexpr (kDpp) return dpp_move<kDppWaveShl1>(v);
         else return shfl(v, rnb);
     }
     // reductions of the new state: maxima, and the admissibility witnesses
@@ -203,7 +222,7 @@ struct March {
                 // a pinned x edge: its ghost's equilibrium streams in instead (nx >= 4:
                 // X == 0 and X == nx - 1 are distinct columns).  Applied as a second
                 // store and in the pending moments, after the streaming stores.
-                const bool pin_lo = P.bc[0] == 2 && X == 0, pin_hi = P.bc[1] == 2 && X == nx - 1;
+                const bool pin_lo = !XPER && P.bc[0] == 2 && X == 0, pin_hi = !XPER && P.bc[1] == 2 && X == nx - 1;
                 // streaming stores (pull semantics: a clamped ghost repeats the edge cell)
                 if (owner) {
                     const unsigned col = (unsigned)X * (unsigned)sizeof(S);
@@ -282,7 +301,7 @@ struct March {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     J[cR1][k] += hq[k];                                             // completes row R-1
-                    J[cR][k] += (C)0.5 * (right(qx[k]) - left(qx[k]));      // x-part of row R
+                    J[cR][k] += (C)0.5 * (right_col(qx[k]) - left_col(qx[k]));   // x-part of row R
                     J[cR2][k] = -hq[k];                                             // starts row R+1
                 }
                 C hx = 0, hy = 0;
@@ -291,8 +310,8 @@ struct March {
                     hy = uy * inv2dx;
                     Dl[cR1] += hy;
                     Vo[cR1] -= hx;
-                    Dl[cR] += (right(ux) - left(ux)) * inv2dx;
-                    Vo[cR] += (right(uy) - left(uy)) * inv2dx;
+                    Dl[cR] += (right_col(ux) - left_col(ux)) * inv2dx;
+                    Vo[cR] += (right_col(uy) - left_col(uy)) * inv2dx;
                     Dl[cR2] = -hy;
                     Vo[cR2] = hx;
                 }
@@ -340,7 +359,7 @@ extern __shared__ __align__(16) unsigned char vlbm_step_lds[];
 // They march in step (one barrier per row), so the halo lines that
 // neighbouring strips both read are fetched from HBM once and served to the
 // second reader from the caches.
-template <typename S, typename C, int EOS, int SENSOR, int DEPTH>
+template <typename S, typename C, int EOS, int SENSOR, int DEPTH, bool XPER>
 __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep St, const S* __restrict__ fin,
                                                    S* __restrict__ fout)
 {
@@ -363,7 +382,7 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
         __syncthreads();
     }
 
-    March<S, C, EOS, SENSOR, DEPTH> m{P, St};
+    March<S, C, EOS, SENSOR, DEPTH, XPER> m{P, St};
     m.in = make_planes(fin, (unsigned)P.plane);
     m.out = make_planes((const S*)fout, (unsigned)P.plane);
     m.ring = ring;
@@ -452,10 +471,13 @@ static hipError_t launch_t(const KParams& p, const KStep& s, const void* fin, vo
     const size_t lds = (size_t)p.wpg * 3 * 16 * kRingW * sizeof(S);
     const S* in = (const S*)fin;
     S* out = (S*)fout;
-#define VLBM_CASE(E, SN)                                                                              \
-    if (p.eos == E && p.sensor == SN) {                                                               \
-        hipLaunchKernelGGL((k_step_d2q4<S, C, E, SN, DEPTH>), grid, block, lds, st, p, s, in, out); \
-        return hipGetLastError();                                                                     \
+#define VLBM_CASE(E, SN)                                                                                     \
+    if (p.eos == E && p.sensor == SN) {                                                                    \
+        if (p.bc[0] == 0)                                                                                  \
+            hipLaunchKernelGGL((k_step_d2q4<S, C, E, SN, DEPTH, true>), grid, block, lds, st, p, s, in, out);  \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_step_d2q4<S, C, E, SN, DEPTH, false>), grid, block, lds, st, p, s, in, out); \
+        return hipGetLastError();                                                                          \
     }
     VLBM_CASE(0, 0) VLBM_CASE(0, 1) VLBM_CASE(0, 2) VLBM_CASE(1, 0) VLBM_CASE(1, 1) VLBM_CASE(1, 2)
 #undef VLBM_CASE
@@ -481,11 +503,11 @@ int step_d2q4_blocks_per_cu(const KParams& p, int prec)
     const size_t l8 = (size_t)p.wpg * 3 * 16 * kRingW * 8, l4 = l8 / 2;
     switch (prec) {
     case PREC_FP64:
-        e = p.deep ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, double, 0, 2, 2>, bs, l8)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, double, 0, 2, 1>, bs, l8);
+        e = p.deep ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, double, 0, 2, 2, false>, bs, l8)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<double, double, 0, 2, 1, false>, bs, l8);
         break;
-    case PREC_FP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, float, 0, 2, 2>, bs, l4); break;
-    case PREC_FP32_MIXED: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, double, 0, 2, 2>, bs, l4); break;
+    case PREC_FP32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, float, 0, 2, 2, false>, bs, l4); break;
+    case PREC_FP32_MIXED: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, double, 0, 2, 2, false>, bs, l4); break;
     }
     return e == hipSuccess ? nb : 0;
 }
