@@ -175,7 +175,9 @@ struct AdjMarch {
                 for (int k = 0; k < 4; ++k) {
                     const C hq = (C)0.5 * qy[k];
                     J1[k] += hq;
-                    J0[k] += (C)0.5 * (from_right(qx[k], kr) - from_left(qx[k], kl));
+                    // flux and velocity come from the loaded column alone: the lane beyond a
+                    // clamped edge loaded the edge column, so no edge select is needed
+                    J0[k] += (C)0.5 * (from_right(qx[k], false) - from_left(qx[k], false));
                     Jn[k] = -hq;
                     if (clo && R == 0) J0[k] -= hq;
                     if (chi && R == ny - 1) J0[k] += hq;
@@ -184,8 +186,8 @@ struct AdjMarch {
                     const C hx = ux * inv2dx, hy = uy * inv2dx;
                     D1 += hy;
                     V1 -= hx;
-                    D0 += (from_right(ux, kr) - from_left(ux, kl)) * inv2dx;
-                    V0 += (from_right(uy, kr) - from_left(uy, kl)) * inv2dx;
+                    D0 += (from_right(ux, false) - from_left(ux, false)) * inv2dx;
+                    V0 += (from_right(uy, false) - from_left(uy, false)) * inv2dx;
                     Dn = -hy;
                     Vn = hx;
                     if (clo && R == 0) { D0 -= hy; V0 += hx; }
@@ -374,7 +376,8 @@ struct AdjMarch {
     }
 };
 
-template <typename S, typename C, int EOS, int SENSOR>
+// XPER: both x edges periodic (no clamped column): the edge selects fold away.
+template <typename S, typename C, int EOS, int SENSOR, bool XPER>
 __global__ void __launch_bounds__(64) k_adj_march(const KParams P, const S* __restrict__ f, const double* __restrict__ norms,
                                                   const S* __restrict__ lam, S* __restrict__ lam_out,
                                                   double* __restrict__ rec)
@@ -417,8 +420,8 @@ __global__ void __launch_bounds__(64) k_adj_march(const KParams P, const S* __re
     if (m.X < 0) cx = P.bc[0] == 0 ? wrap_index(m.X, m.nx) : 0;
     else if (m.X >= m.nx) cx = P.bc[1] == 0 ? wrap_index(m.X, m.nx) : m.nx - 1;
     m.colx = (unsigned)cx;
-    m.atL = P.bc[0] == 1 && m.X == 0;
-    m.atR = P.bc[1] == 1 && m.X == m.nx - 1;
+    m.atL = !XPER && P.bc[0] == 1 && m.X == 0;
+    m.atR = !XPER && P.bc[1] == 1 && m.X == m.nx - 1;
     m.kl = m.atL;
     m.kr = m.atR;
     m.owner = m.lane >= halo && m.lane < halo + P.strip_w && m.X < m.nx;
@@ -603,7 +606,10 @@ static hipError_t march_t(const KParams& p, const void* f_n, const double* norms
     S* lo = (S*)lam_n;
 #define VLBM_AM(E, SN)                                                                                         \
     if (p.eos == E && p.sensor == SN) {                                                                        \
-        hipLaunchKernelGGL((k_adj_march<S, C, E, SN>), dim3(nb), dim3(64), 0, st, p, f, norms, lam, lo, rec); \
+        if (p.bc[0] == 0)                                                                                      \
+            hipLaunchKernelGGL((k_adj_march<S, C, E, SN, true>), dim3(nb), dim3(64), 0, st, p, f, norms, lam, lo, rec); \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_adj_march<S, C, E, SN, false>), dim3(nb), dim3(64), 0, st, p, f, norms, lam, lo, rec); \
         if (SN != 0) hipLaunchKernelGGL((k_adjm_fix<S, C, E>), dim3(1), dim3(kFixThreads), 0, st, p, f, rec, nb, lo);  \
         return hipGetLastError();                                                                              \
     }
