@@ -77,8 +77,8 @@ struct March {
     // row R in buf[PH] and the loads of rows R+1 and R+2 in the other two, so
     // twice the bytes are in flight per wavefront.  FP32 storage always has the
     // registers for it; with FP64 storage it costs the second wavefront per SIMD
-    // (256 VGPRs and 18 AGPRs), which pays only on grids too small to fill the
-    // second one anyway.
+    // (255 VGPRs and up to 14 AGPRs), which pays only on grids too small to fill
+    // the second one anyway.
     static constexpr int DEPTH = DEPTH_;
     S buf[DEPTH == 2 ? 3 : 1][16];
     // x-neighbour values: DPP wavefront shifts (VALU) where a wavefront runs
