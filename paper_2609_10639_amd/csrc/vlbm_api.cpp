@@ -173,6 +173,16 @@ vlbm_status run_batch(vlbm_ctx* ctx, long long count, double t_end, long long* e
     return VLBM_OK;
 }
 
+// Elements per population plane: the cells rounded up to 64, plus 1 KB.  Without
+// the extra kilobyte the planes of a power-of-two grid start a power of two
+// apart, and the 16 row streams of the D2Q4 march meet in the same HBM
+// channels (measured on MI355X at 4096^2: FP64 +4.5 %, FP32 +2 %; D1Q2 +2 %;
+// 512 B and 1.5 KB did about as well, 4 KB was slower).
+long long padded_plane(long long ncell, long long esize)
+{
+    return (ncell + 63) / 64 * 64 + 1024 / esize;
+}
+
 bool check_config(const vlbm_config* c, std::string& why)
 {
     if (c->dim != 1 && c->dim != 2) return why = "dim must be 1 or 2", false;
@@ -226,8 +236,8 @@ bool check_config(const vlbm_config* c, std::string& why)
         // the D2Q4 marches address four planes from one buffer resource with
         // 32-bit offsets: 4 padded planes must fit in 4 GiB (2^27 cells in FP64,
         // 2^28 with FP32 storage)
-        const long long plane = (c->nx * c->ny + 63) / 64 * 64;
         const long long esize = c->precision == VLBM_FP64 ? 8 : 4;
+        const long long plane = padded_plane(c->nx * c->ny, esize);
         if (4 * plane * esize > (1LL << 32))
             return why = "grid too large for the D2Q4 kernels' 32-bit offsets (2^27 cells in FP64, 2^28 with FP32 storage)",
                    false;
@@ -259,7 +269,7 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
     ctx->fp32 = ctx->prec != PREC_FP64;
     ctx->esize = ctx->fp32 ? 4 : 8;
     ctx->ncell = cfg->nx * cfg->ny;
-    ctx->plane = (ctx->ncell + 63) / 64 * 64;
+    ctx->plane = padded_plane(ctx->ncell, ctx->esize);
 
     KParams& p = ctx->kp;
     p.dim = cfg->dim;

