@@ -95,7 +95,11 @@ typedef struct {
                                 0: link speed frozen at c_fixed (no retarget, no landing) */
     double c_fixed;          /* link speed when retarget_every == 0 */
     int32_t sensor;          /* VLBM_SENSOR_*: OFF uses beta_const; A = Eq. 34; B = Eq. 35 */
-    double beta_const, beta_min, beta_max, c_sensor, eps_theta;
+    double beta_const, beta_min, beta_max, c_sensor;
+    double eps_theta;        /* regulariser of the Ducros ratio (Eq. 33), dimensionless: dilatation and
+                                vorticity enter in lattice units, dt = dx/c times their central
+                                differences at the step's link speed, so beta is the same in any units
+                                of length and time.  > 0; 1e-10 is the value the tests use */
     int32_t precision;       /* VLBM_FP64, VLBM_FP32 or VLBM_FP32_MIXED (populations and per-cell
                                 arithmetic; clock, dt reduction and totals stay FP64) */
     void* stream;            /* hipStream_t, or NULL for the default stream */

@@ -102,7 +102,7 @@ def make_config(**kw):
     """Build an OrcConfig from keyword arguments (same names as the fields)."""
     d = dict(dim=1, nx=100, ny=1, dx=0.01, bc=(OUTFLOW,) * 4, eos=IDEAL, gamma=1.4, vdw_a=0.0,
              vdw_b=0.0, vdw_R=1.0, cfl=0.5, retarget_every=1, c_fixed=0.0, sensor=SENSOR_AUTO,
-             beta_const=1.0, beta_min=0.75, beta_max=1.0, c_sensor=4.0, eps_theta=1e-12)
+             beta_const=1.0, beta_min=0.75, beta_max=1.0, c_sensor=4.0, eps_theta=1e-10)
     d.update(kw)
     cfg = OrcConfig()
     for k, v in d.items():

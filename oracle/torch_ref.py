@@ -115,9 +115,10 @@ class Frozen:
         s = torch.where(pos, torch.sqrt(torch.where(pos, m, torch.ones_like(m))), torch.zeros_like(m))
         sbar = self.box(s)
         if self.sensor == 2 and D == 2:
-            h2 = 2.0 * g["dx"]
-            dil = (self.shift(u[0], 1, 0) - self.shift(u[0], -1, 0)) / h2 + (self.shift(u[1], 0, 1) - self.shift(u[1], 0, -1)) / h2
-            vort = (self.shift(u[1], 1, 0) - self.shift(u[1], -1, 0)) / h2 - (self.shift(u[0], 0, 1) - self.shift(u[0], 0, -1)) / h2
+            # dilatation and vorticity by central differences, times dt = dx/c (lattice units)
+            h2, dt = 2.0 * g["dx"], g["dx"] / self.c
+            dil = dt * ((self.shift(u[0], 1, 0) - self.shift(u[0], -1, 0)) / h2 + (self.shift(u[1], 0, 1) - self.shift(u[1], 0, -1)) / h2)
+            vort = dt * ((self.shift(u[1], 1, 0) - self.shift(u[1], -1, 0)) / h2 - (self.shift(u[0], 0, 1) - self.shift(u[0], 0, -1)) / h2)
             theta = dil * dil / (dil * dil + vort * vort + g["eps_theta"])
             thbar = self.box(theta)
         else:

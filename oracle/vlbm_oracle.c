@@ -33,7 +33,12 @@
  *     holds a fixed state W_b at equilibrium, so the populations that stream
  *     in across that edge are f^eq_i(W_b) at the current link speed (Eq. 20);
  *     the sensor's stencils treat the edge like an outflow edge;
- *   - with retarget_every = K > 1 a retarget is forced whenever s_max > c.
+ *   - with retarget_every = K > 1 a retarget is forced whenever s_max > c;
+ *   - the Ducros ratio (Eq. 33) takes dilatation and vorticity in lattice
+ *     units, dt times their central differences (dt = dx/c at the step's
+ *     link speed), so that its regulariser eps is a dimensionless number and
+ *     beta does not depend on the units of time or length, like every other
+ *     ratio of the sensor (Eqs. 29-31).
  *
  * Directions: i = 0 (+x), 1 (-x), 2 (+y), 3 (-y).  Components:
  * k = 0 rho, 1..D momentum, D+1 total energy rho*E.
@@ -425,13 +430,17 @@ static void sweep_beta(orc_state* s)
             long x = c % g->nx, y = c / g->nx;
             long xp = nb_cell(s, x, y, 1, 0), xm = nb_cell(s, x, y, -1, 0);
             long yp = nb_cell(s, x, y, 0, 1), ym = nb_cell(s, x, y, 0, -1);
+            /* central differences (Eq. 32) times the time step dt = dx/c:
+             * dilatation and vorticity in lattice units, so that eps is a
+             * dimensionless number (reading of Eq. 33) */
+            double dt = g->dx / s->c;
             double h2 = 2.0 * g->dx;
             double dux_dx = (UV(s, 0, xp) - UV(s, 0, xm)) / h2;
             double duy_dy = (UV(s, 1, yp) - UV(s, 1, ym)) / h2;
             double duy_dx = (UV(s, 1, xp) - UV(s, 1, xm)) / h2;
             double dux_dy = (UV(s, 0, yp) - UV(s, 0, ym)) / h2;
-            double dil = dux_dx + duy_dy;
-            double vort = duy_dx - dux_dy;
+            double dil = dt * (dux_dx + duy_dy);
+            double vort = dt * (duy_dx - dux_dy);
             s->theta[c] = dil * dil / (dil * dil + vort * vort + g->eps_theta);
         }
         box_filter(s, s->theta, s->thetabar);

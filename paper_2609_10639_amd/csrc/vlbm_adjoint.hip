@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_p2(KParams p, const double* _
     constexpr int NK = D + 2;
     const Geo<D> G = make_geo<D>(p);
     const long long ncell = (long long)p.nx * p.ny;
-    const C inv2dx = (C)(0.5 / p.dx);
+    const C inv2c = (C)(0.5 / p.c_fixed);   // the gate's differences in lattice units (dt = dx/c)
     C invM[4];
     for (int k = 0; k < NK; ++k) {
         const double M = norm_max(norms, 1 + k);
@@ -190,8 +190,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_p2(KParams p, const double* _
             const C* ux = aux + (L::A1 + D * NK + 0) * ncell;
             const C* uy = aux + (L::A1 + D * NK + 1) * ncell;
             const int xp = G.cell(x, y, 1, 0), xm = G.cell(x, y, -1, 0), yp = G.cell(x, y, 0, 1), ym = G.cell(x, y, 0, -1);
-            dil = (ux[xp] - ux[xm]) * inv2dx + (uy[yp] - uy[ym]) * inv2dx;
-            vort = (uy[xp] - uy[xm]) * inv2dx - (ux[yp] - ux[ym]) * inv2dx;
+            dil = (ux[xp] - ux[xm]) * inv2c + (uy[yp] - uy[ym]) * inv2c;
+            vort = (uy[xp] - uy[xm]) * inv2c - (ux[yp] - ux[ym]) * inv2c;
             th = dil * dil / (dil * dil + vort * vort + (C)p.eps_theta);
         }
         aux[(L::A2 + NK + 0) * ncell + c] = s;
@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_p5(KParams p, const S* __rest
     const Geo<D> G = make_geo<D>(p);
     const long long ncell = (long long)p.nx * p.ny;
     const Gas<C> g = make_gas<C>(p);
-    const C inv2c = (C)(0.5 / p.c_fixed), inv2dx = (C)(0.5 / p.dx);
+    const C inv2c = (C)(0.5 / p.c_fixed);
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < ncell;
          c += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(c % p.nx), y = (int)(c / p.nx);
@@ -442,8 +442,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_p5(KParams p, const S* __rest
             if constexpr (SENSOR == 2 && D == 2) {
                 const C* dilb = aux + (L::A4 + NK + 0) * ncell;
                 const C* vortb = aux + (L::A4 + NK + 1) * ncell;
-                ub[0] = (diff_t<C, D>(G, dilb, x, y, 1, 0) - diff_t<C, D>(G, vortb, x, y, 0, 1)) * inv2dx;
-                ub[1] = (diff_t<C, D>(G, dilb, x, y, 0, 1) + diff_t<C, D>(G, vortb, x, y, 1, 0)) * inv2dx;
+                ub[0] = (diff_t<C, D>(G, dilb, x, y, 1, 0) - diff_t<C, D>(G, vortb, x, y, 0, 1)) * inv2c;
+                ub[1] = (diff_t<C, D>(G, dilb, x, y, 0, 1) + diff_t<C, D>(G, vortb, x, y, 1, 0)) * inv2c;
             }
         }
         closure_adj<C, EOS, D>(g, W, Qb, ub, Wb);

@@ -47,7 +47,7 @@ struct AdjMarch {
                                 // completed rows (LDS ring): written when row R-1 completes, read by
                                 // stage C (rows R-2, R-3) and stage D (row R-3)
     Gas<C> g;
-    C inv2c, inv2dx, invM[4], csen, bspan, bmax, eps;
+    C inv2c, invM[4], csen, bspan, bmax, eps;   // inv2c = 1/(2c) also scales the gate's differences
     int nx, ny, y0, y1, Rb, Re;
     long long ncell;
     bool clo, chi;              // clamped y-low / y-high boundaries
@@ -183,11 +183,11 @@ struct AdjMarch {
                     if (chi && R == ny - 1) J0[k] += hq;
                 }
                 if constexpr (SENSOR == 2) {
-                    const C hx = ux * inv2dx, hy = uy * inv2dx;
+                    const C hx = ux * inv2c, hy = uy * inv2c;   // lattice units (dt = dx/c)
                     D1 += hy;
                     V1 -= hx;
-                    D0 += (from_right(ux, false) - from_left(ux, false)) * inv2dx;
-                    V0 += (from_right(uy, false) - from_left(uy, false)) * inv2dx;
+                    D0 += (from_right(ux, false) - from_left(ux, false)) * inv2c;
+                    V0 += (from_right(uy, false) - from_left(uy, false)) * inv2c;
                     Dn = -hy;
                     Vn = hx;
                     if (clo && R == 0) { D0 -= hy; V0 += hx; }
@@ -296,10 +296,10 @@ struct AdjMarch {
                     QYm[k] -= bot ? (C)0 : hj;
                 }
                 if constexpr (SENSOR == 2) {
-                    // u_x-bar = (T_x dil-bar - T_y vort-bar)/(2dx), u_y-bar = (T_y dil-bar + T_x vort-bar)/(2dx)
-                    UXx = inv2dx * tdiff_x(dilb);
-                    UYx = inv2dx * tdiff_x(vortb);
-                    const C vx = -inv2dx * vortb, dy = inv2dx * dilb;
+                    // u_x-bar = (T_x dil-bar - T_y vort-bar)/(2c), u_y-bar = (T_y dil-bar + T_x vort-bar)/(2c)
+                    UXx = inv2c * tdiff_x(dilb);
+                    UYx = inv2c * tdiff_x(vortb);
+                    const C vx = -inv2c * vortb, dy = inv2c * dilb;
                     UXp += top ? (C)0 : vx;
                     UYp += top ? (C)0 : dy;
                     UX0 += (top ? vx : (C)0) - (bot ? vx : (C)0);
@@ -397,7 +397,6 @@ __global__ void __launch_bounds__(64) k_adj_march(const KParams P, const S* __re
         for (int v = 0; v < 9; ++v) hring[sl][v][threadIdx.x] = (C)0;
     m.g = make_gas<C>(P);
     m.inv2c = (C)(0.5 / P.c_fixed);
-    m.inv2dx = (C)(0.5 / P.dx);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         double M = norms[1 + k];

@@ -57,7 +57,7 @@ struct March {
     Planes in, out;
     S (*ring)[16][kRingW];
     Gas<C> g;
-    C r, inv2c, inv2dx, invM[4];
+    C r, inv2c, invM[4];   // inv2c = 1/(2c): also scales the velocity differences of the gate
     C eoff;            // energy gauge of the stored populations (physical e = e_stored + eoff)
     int nx, ny, y0, y1, Rb, Re;
     bool clo, chi;
@@ -306,12 +306,14 @@ struct March {
                 }
                 C hx = 0, hy = 0;
                 if constexpr (SENSOR == 2) {
-                    hx = ux * inv2dx;
-                    hy = uy * inv2dx;
+                    // dilatation and vorticity in lattice units: (u(x+e) - u(x-e))/(2c),
+                    // i.e. dt times the central difference (dt = dx/c)
+                    hx = ux * inv2c;
+                    hy = uy * inv2c;
                     Dl[cR1] += hy;
                     Vo[cR1] -= hx;
-                    Dl[cR] += (right_col(ux) - left_col(ux)) * inv2dx;
-                    Vo[cR] += (right_col(uy) - left_col(uy)) * inv2dx;
+                    Dl[cR] += (right_col(ux) - left_col(ux)) * inv2c;
+                    Vo[cR] += (right_col(uy) - left_col(uy)) * inv2c;
                     Dl[cR2] = -hy;
                     Vo[cR2] = hx;
                 }
@@ -395,7 +397,6 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
         const double M = red_fold(St, 1 + k);
         m.invM[k] = M > 0.0 ? (C)(1.0 / M) : (C)0;
     }
-    m.inv2dx = (C)(0.5 / P.dx);
     m.eoff = (C)P.e_off;
     m.nx = P.nx;
     m.ny = P.ny;

@@ -116,6 +116,14 @@ def centres(n, lo, hi):
 SENSOR_1D = dict(beta_min=0.75, beta_max=1.0, c_sensor=4.0)
 SENSOR_2D = dict(beta_min=0.7, beta_max=1.0, c_sensor=16.0)
 
+# Regulariser of the Ducros ratio (Eq. 33), a dimensionless number: dilatation
+# and vorticity enter in lattice units (dt times their central differences).
+# 1e-10 is a velocity difference of 1e-5 link speeds across one cell, squared:
+# far below any compression the gate has to see, far above the squared
+# rounding of FP32 populations (about 1e-14), so that flow that is quiescent up
+# to rounding keeps theta near 0 in every precision.
+EPS_THETA = 1e-10
+
 # --------------------------------------------------------------- 1-D problems
 
 

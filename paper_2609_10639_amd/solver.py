@@ -29,7 +29,7 @@ class Solver:
 
     DEFAULTS = dict(dim=1, nx=100, ny=1, dx=0.01, bc=(1, 1, 1, 1), eos=0, gamma=1.4, vdw_a=0.0, vdw_b=0.0,
                     vdw_R=1.0, e_offset=0.0, cfl=0.5, retarget_every=1, c_fixed=0.0, sensor=3, beta_const=1.0, beta_min=0.75,
-                    beta_max=1.0, c_sensor=4.0, eps_theta=1e-12, precision="fp64")
+                    beta_max=1.0, c_sensor=4.0, eps_theta=1e-10, precision="fp64")
 
     def __init__(self, stream=None, **kw):
         torch = _torch()

@@ -58,7 +58,7 @@ def gresho_case(n=100, sensor="B"):
     stable constant beta 0.995 (the paper's rule for beta_min), or that
     constant beta alone."""
     W0, dx = pr.gresho(n)
-    cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, eps_theta=1e-12, **pr.IDEAL_MONO.config())
+    cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, **pr.IDEAL_MONO.config())
     if sensor == "B":
         cfg.update(sensor=2, beta_min=0.995, beta_max=1.0, c_sensor=16.0)
     else:
@@ -122,7 +122,7 @@ def tube_config(case, n):
     Sensor A with (0.75, 1, 4) (Sec. IV.C, reused for Sec. IV.D)."""
     build, gas, t_end = _tube(case)
     W0, dx = build(n)
-    cfg = dict(dim=1, nx=n, ny=1, dx=dx, bc=(1, 1, 1, 1), cfl=0.8, sensor=1, eps_theta=1e-12,
+    cfg = dict(dim=1, nx=n, ny=1, dx=dx, bc=(1, 1, 1, 1), cfl=0.8, sensor=1,
                **pr.SENSOR_1D, **gas.config())
     return W0, cfg, t_end
 

@@ -93,7 +93,7 @@ def riemann_2d(config, printed, beta_min=None):
     gas = pr.RIEMANN_GAS[config]
     W0, dx = pr.riemann2d(n, config)
     sensor = dict(pr.SENSOR_2D, **({} if beta_min is None else dict(beta_min=beta_min)))
-    cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2, eps_theta=1e-12, **sensor,
+    cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2, **sensor,
                **gas.config())
     t0 = time.time()
     vlbm_W = vlbm_run(W0, cfg, t_end)

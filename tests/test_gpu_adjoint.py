@@ -36,7 +36,7 @@ def _say(*a):
 def _vortex_cfg(n, c=None):
     W0, dx = pr.vortex_perturbed(n, amplitude=1e-3, seed=42)
     cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), retarget_every=0,
-               c_fixed=c if c else 2.93 / 0.45, sensor=2, **pr.SENSOR_2D, eps_theta=1e-12, beta_const=1.0,
+               c_fixed=c if c else 2.93 / 0.45, sensor=2, **pr.SENSOR_2D, eps_theta=pr.EPS_THETA, beta_const=1.0,
                **pr.IDEAL_AIR.config())
     return W0, cfg
 
@@ -67,16 +67,16 @@ CASES = {
     "vortex_periodic_B": lambda: _vortex_cfg(48),
     "riemann12_outflow_B": lambda: (_noisy(pr.riemann2d(40, 12)[0]),
                                     dict(dim=2, nx=40, ny=40, dx=1 / 40, bc=(1, 1, 1, 1), retarget_every=0, c_fixed=4.5,
-                                         sensor=2, **pr.SENSOR_2D, eps_theta=1e-12, beta_const=1.0,
+                                         sensor=2, **pr.SENSOR_2D, eps_theta=pr.EPS_THETA, beta_const=1.0,
                                          **pr.IDEAL_AIR.config())),
     "bzt_mixed_B": lambda: (_noisy(pr.bzt_extrusion(32)[0]),
                             dict(dim=2, nx=32, ny=32, dx=1 / 32, bc=(1, 1, 0, 0), retarget_every=0, c_fixed=1.9,
-                                 sensor=2, **pr.SENSOR_2D, eps_theta=1e-12, beta_const=1.0,
+                                 sensor=2, **pr.SENSOR_2D, eps_theta=pr.EPS_THETA, beta_const=1.0,
                                  **pr.VDW_REDUCED_CV50.config())),
     "vortex_A": lambda: (_vortex_cfg(40)[0], dict(_vortex_cfg(40)[1], sensor=1)),
     "vortex_const_beta": lambda: (_vortex_cfg(40)[0], dict(_vortex_cfg(40)[1], sensor=0, beta_const=0.9)),
     "sod_1d": lambda: (_noisy(pr.sod(128)[0]), dict(dim=1, nx=128, ny=1, dx=1 / 128, bc=(1, 1, 1, 1), retarget_every=0,
-                                             c_fixed=5.0, sensor=1, **pr.SENSOR_1D, eps_theta=1e-12,
+                                             c_fixed=5.0, sensor=1, **pr.SENSOR_1D, eps_theta=pr.EPS_THETA,
                                              beta_const=1.0, **pr.IDEAL_AIR.config())),
 }
 
@@ -212,7 +212,7 @@ def test_fused_and_multipass_adjoint_step(precision, tol, shape, bc, sensor, mon
     W0 = pr.riemann2d(n, 12)[0][:, :ny, :nx].copy()
     W0 = W0 + 1e-3 * np.abs(W0).max(axis=(1, 2), keepdims=True) * pr.gaussian(11, W0.size).reshape(W0.shape)
     cfg = dict(dim=2, nx=nx, ny=ny, dx=1.0 / n, bc=bc, retarget_every=0, c_fixed=4.5, sensor=sensor,
-               **pr.SENSOR_2D, eps_theta=1e-12, beta_const=0.9, **pr.IDEAL_AIR.config())
+               **pr.SENSOR_2D, eps_theta=pr.EPS_THETA, beta_const=0.9, **pr.IDEAL_AIR.config())
     ref, errs = None, []
     for multipass in ("0", "1"):
         monkeypatch.setenv("VLBM_ADJ_MULTIPASS", multipass)

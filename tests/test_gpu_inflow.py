@@ -60,7 +60,7 @@ def _stream_case(nx, ny, bc, speed):
     centre = (0.3 * Lx, 0.5 * ny * dx) if speed > 0 else (0.7 * Lx, 0.5 * ny * dx)
     W0, Winf = pr.vortex_in_stream(nx, ny, dx, speed=speed, centre=centre)
     cfg = dict(dim=2, nx=nx, ny=ny, dx=dx, bc=bc, bc_state=(tuple(Winf), tuple(Winf)), cfl=0.45, sensor=2,
-               eps_theta=1e-12, **pr.SENSOR_2D, **pr.IDEAL_AIR.config())
+               **pr.SENSOR_2D, **pr.IDEAL_AIR.config())
     return W0, cfg
 
 

@@ -44,7 +44,7 @@ def test_uniform_stream_stays_uniform_1d(u, sensor):
     Wb = tuple(W0[:, 0, 0])
     bc = (2, 1, 1, 1) if u > 0 else (1, 2, 1, 1)
     o = oracle_for(dict(dim=1, nx=64, ny=1, dx=dx, bc=bc, bc_state=(Wb, Wb), cfl=0.8, sensor=sensor,
-                        beta_const=0.9, eps_theta=1e-12, **pr.SENSOR_1D, **IDEAL), W0)
+                        beta_const=0.9, **pr.SENSOR_1D, **IDEAL), W0)
     for _ in range(40):
         o.step()
     assert np.abs(o.W() - W0).max() <= 1e-13 * np.abs(W0).max()
@@ -58,7 +58,7 @@ def test_uniform_stream_stays_uniform_2d(bc):
                       np.full((n, n + 5), v))
     Wb = tuple(W0[:, 0, 0])
     o = oracle_for(dict(dim=2, nx=n + 5, ny=n, dx=1.0 / n, bc=bc, bc_state=(Wb, Wb), cfl=0.45, sensor=2,
-                        eps_theta=1e-12, **pr.SENSOR_2D, **IDEAL), W0)
+                        **pr.SENSOR_2D, **IDEAL), W0)
     for _ in range(30):
         o.step()
     assert np.abs(o.W() - W0).max() <= 1e-13 * np.abs(W0).max()
@@ -69,7 +69,7 @@ def test_pinned_equals_outflow_while_the_edge_is_quiet():
     inflow edge to the free stream gives the outflow result bit for bit until
     non-equilibrium content reaches the edge cell (a few steps here)."""
     W0, Winf = pr.vortex_in_stream(80, 40, 0.25, speed=2.0, centre=(12.0, 5.0))
-    base = dict(dim=2, nx=80, ny=40, dx=0.25, cfl=0.45, sensor=2, eps_theta=1e-12, **pr.SENSOR_2D, **IDEAL)
+    base = dict(dim=2, nx=80, ny=40, dx=0.25, cfl=0.45, sensor=2, **pr.SENSOR_2D, **IDEAL)
     a = oracle_for(dict(base, bc=(1, 1, 0, 0)), W0)
     b = oracle_for(dict(base, bc=(2, 1, 0, 0), bc_state=(tuple(Winf), None)), W0)
     for _ in range(3):
@@ -98,7 +98,7 @@ def shu_osher_config(n, sensor, inflow="pinned"):
     beta = 0.9; the left (supersonic inflow) end pinned to the inflow state,
     or outflow as stated for both ends; the right end outflow."""
     W0, dx = pr.shu_osher(n)
-    cfg = dict(dim=1, nx=n, ny=1, dx=dx, cfl=0.8, eps_theta=1e-12, **IDEAL)
+    cfg = dict(dim=1, nx=n, ny=1, dx=dx, cfl=0.8, **IDEAL)
     cfg.update(dict(sensor=1, **pr.SENSOR_1D) if sensor == "A" else dict(sensor=0, beta_const=0.9))
     if inflow == "pinned":
         cfg.update(bc=(2, 1, 1, 1), bc_state=(tuple(W0[:, 0, 0]), None))

@@ -26,7 +26,7 @@ def _case(n, bc, eos, sensor, noise=1e-3, seed=3):
         W = W + noise * pr.gaussian(seed, W.size).reshape(W.shape)
         c = 4.0 * 10.0 / n * n / 10.0 + 3.0
     cfg = dict(dim=2, nx=n, ny=n, dx=10.0 / n, bc=bc, retarget_every=0, c_fixed=c, sensor=sensor,
-               beta_const=0.8, **pr.SENSOR_2D, eps_theta=1e-12, **gas.config())
+               beta_const=0.8, **pr.SENSOR_2D, eps_theta=pr.EPS_THETA, **gas.config())
     return W, cfg
 
 
@@ -50,7 +50,7 @@ def test_torch_forward_matches_c_oracle(bc, eos, sensor):
 def test_one_dimensional_forward_matches_c_oracle():
     W0, dx = pr.sod(64)
     cfg = dict(dim=1, nx=64, ny=1, dx=dx, bc=(1, 1, 1, 1), retarget_every=0, c_fixed=5.0, sensor=1,
-               **pr.SENSOR_1D, eps_theta=1e-12, beta_const=1.0, **pr.IDEAL_AIR.config())
+               **pr.SENSOR_1D, eps_theta=pr.EPS_THETA, beta_const=1.0, **pr.IDEAL_AIR.config())
     o = core.Oracle(**cfg)
     o.init(W0)
     fr = Frozen(cfg)

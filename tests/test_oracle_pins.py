@@ -355,10 +355,106 @@ def test_sensor_ducros_gate():
             o.init(W)
             betas[name, sensor] = o.beta()
     inner = (slice(3, -3), slice(3, -3))
-    assert np.allclose(betas["dil", 2][inner], betas["dil", 1][inner], rtol=0, atol=1e-12)
+    # theta = d^2/(d^2 + eps) with d = dt dil ~ 0.014 in lattice units: 1 - theta ~ 5e-7
+    assert np.allclose(betas["dil", 2][inner], betas["dil", 1][inner], rtol=0, atol=1e-6)
     assert np.all(betas["dil", 1][inner] < 1.0)
     assert np.allclose(betas["rot", 2][inner], 1.0, rtol=0, atol=1e-12)
     assert np.all(betas["rot", 1][inner] < 1.0)
+
+
+def _gate_from_betas(W, dx, **kw):
+    """theta_bar of the oracle's Ducros gate recovered from its beta fields:
+    Sensor B and Sensor A differ only by the factor theta_bar inside the clip
+    (Eqs. 34-35), so where C s_bar lies strictly inside (0, 1),
+    theta_bar = (beta_max - beta_B)/(beta_max - beta_A).  Returns theta_bar,
+    chi_A and the link speed the sensor ran at."""
+    n = W.shape[-1]
+    betas = {}
+    for sensor in (1, 2):
+        o = core.Oracle(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), sensor=sensor, **kw)
+        o.init(W)
+        betas[sensor] = o.beta()
+    c = o.clock()[1]
+    bmax, bmin = o.cfg.beta_max, o.cfg.beta_min
+    chi_a = (bmax - betas[1]) / (bmax - bmin)
+    return (bmax - betas[2]) / (bmax - betas[1]), chi_a, c
+
+
+def _linear_flow(n, a, b, c, d, q=0.0):
+    """rho = 1, P = 1, u = (a x + b y, c x + d y + q x^2) on [-1/2, 1/2]^2.
+    Central differences are exact for this field: dilatation = a + d and
+    vorticity = c - b + 2 q x at every interior cell (up to rounding)."""
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h - 0.5
+    X, Y = np.meshgrid(x, x)
+    W = pr.conserved(pr.IDEAL_AIR, np.ones((n, n)), a * X + b * Y, np.ones((n, n)), c * X + d * Y + q * X * X)
+    return W, h, x
+
+
+def test_ducros_ratio_of_a_linear_field():
+    # u = (a x + b y, c x + d y): dil = a + d, vort = c - b, uniform, so the
+    # filtered ratio equals the ratio itself in the interior (Eq. 33), with
+    # dilatation and vorticity in the lattice's units (one time step, dx/c):
+    # theta = (dt dil)^2 / ((dt dil)^2 + (dt vort)^2 + eps).
+    n = 24
+    a, b, c, d = 0.5, 0.35, -0.15, 0.1
+    W, h, _ = _linear_flow(n, a, b, c, d)
+    inner = (slice(3, -3), slice(3, -3))
+    for eps in (1e-12, 4e-5):
+        th, chi_a, cl = _gate_from_betas(W, h, eps_theta=eps, c_sensor=2.0)
+        assert np.all((chi_a[inner] > 0.02) & (chi_a[inner] < 0.98)), chi_a[inner]   # unclipped
+        dt = h / cl
+        dil, vort = dt * (a + d), dt * (c - b)
+        expect = dil * dil / (dil * dil + vort * vort + eps)
+        assert np.allclose(th[inner], expect, rtol=1e-9, atol=0), (eps, th[inner].min(), th[inner].max(), expect)
+    # the regulariser matters at eps = 4e-5 (so the test fixes its units), and
+    # a flipped vorticity sign (c + b) would move theta from 0.59 to 0.90
+    assert expect < 0.9 * (a + d) ** 2 / ((a + d) ** 2 + (c - b) ** 2)
+    assert abs((a + d) ** 2 / ((a + d) ** 2 + (c + b) ** 2) - (a + d) ** 2 / ((a + d) ** 2 + (c - b) ** 2)) > 0.3
+
+
+def test_ducros_ratio_is_box_filtered():
+    # vort = c - b + 2 q x varies in x and crosses zero inside the domain, so
+    # theta(x) has a sharp peak; the gate uses its box filter (Eq. 33):
+    # theta_bar(x) = theta(x - h)/4 + theta(x)/2 + theta(x + h)/4 (y-independent).
+    n = 32
+    a, b, c, d, q = 0.3, 0.2, -0.1, 0.1, 1.6
+    W, h, x = _linear_flow(n, a, b, c, d, q)
+    th, chi_a, cl = _gate_from_betas(W, h, c_sensor=2.0)
+    inner = (slice(3, -3), slice(3, -3))
+    assert np.all((chi_a[inner] > 0.02) & (chi_a[inner] < 0.98)), chi_a[inner]
+    dt = h / cl
+
+    def theta(xx):
+        dil, vort = dt * (a + d), dt * (c - b + 2.0 * q * xx)
+        return dil * dil / (dil * dil + vort * vort + pr.EPS_THETA)
+
+    expect = 0.25 * theta(x - h) + 0.5 * theta(x) + 0.25 * theta(x + h)
+    expect = np.broadcast_to(expect, (n, n))
+    assert np.allclose(th[inner], expect[inner], rtol=1e-9, atol=1e-12)
+    # without the filter theta_bar would be theta itself: far off near the peak
+    unfiltered = np.broadcast_to(theta(x), (n, n))
+    assert np.abs(unfiltered[inner] - expect[inner]).max() > 0.01
+
+
+def test_ducros_gate_is_unit_free():
+    # Changing the unit of time by lam maps u -> u/lam, P -> P/lam^2,
+    # rho E -> rho E/lam^2; the scheme is equivariant (c -> c/lam, dt -> lam dt)
+    # and every part of the sensor is a dimensionless ratio (Eqs. 29-33 with
+    # dilatation and vorticity in lattice units), so beta is unchanged.
+    n = 24
+    W, h, _ = _linear_flow(n, 0.3, 0.2, -0.1, 0.1, 1.6)
+    W[0] *= 1.0 + 0.1 * np.sin(np.arange(n) / 3.0)[None, :]   # a density gradient too
+    betas = []
+    for lam in (1.0, 1000.0):
+        Wl = W.copy()
+        Wl[1:3] /= lam
+        Wl[3] /= lam * lam
+        o = core.Oracle(dim=2, nx=n, ny=n, dx=h, bc=(1, 1, 1, 1), sensor=2, eps_theta=1e-4, c_sensor=2.0)
+        o.init(Wl)
+        betas.append(o.beta())
+    assert np.all(betas[0] < 1.0)
+    assert np.allclose(betas[0], betas[1], rtol=0, atol=1e-12)
 
 
 def test_sensor_first_order_in_dx():

@@ -106,7 +106,7 @@ def shock_vortex_config(case, nx, strength=2.0):
     W0, dx, W_in = pr.shock_vortex(case, nx, ny, strength=strength)
     gas = pr.SHOCK_VORTEX[case]["gas"]
     cfg = dict(dim=2, nx=nx, ny=ny, dx=dx, bc=(2, 1, 0, 0), bc_state=(tuple(W_in), None), cfl=0.45, sensor=2,
-               eps_theta=1e-12, **pr.SENSOR_2D, **gas.config())
+               **pr.SENSOR_2D, **gas.config())
     return W0, cfg, pr.SHOCK_VORTEX[case]["t_end"]
 
 
