@@ -1,37 +1,46 @@
 """Benchmark of the VLBM hot path on one MI355X.
 
-Headline workload: the 2-D isentropic vortex (periodic [0,10]^2, strength 5,
-background flow (1,1), ideal gas gamma = 1.4, Sensor B, CFL 0.45) on its
-largest grid, 1024^2, FP64.  A step is one fused D2Q4 lattice update of the
+Headline workload: the four-quadrant Riemann problem, configuration 12 of
+Sec. IV.E, on [0,1]^2 at 4096^2 cells, outflow edges, ideal gas gamma = 1.4,
+D2Q4 with Sensor B (beta_min 0.7, beta_max 1, C 16), CFL 0.45 with the link
+speed retargeted every step, FP32 populations and FP32 arithmetic (clock,
+reductions and totals in FP64).  A step is one fused D2Q4 lattice update of the
 whole grid (moments, EOS closure, retarget + reprojection, sensor, collision,
 streaming and the reductions for the next step), launched through the C ABI;
-`value` is lattice updates per second (MLUPS) of that step.
+`value` is lattice updates per second (MLUPS) over the K timed steps, the
+populations resident in HBM when the timed region starts.
 
 Beside it on the same JSON line:
-  roofline      the fused step kernel against the 8 TB/s HBM peak, from the
-                algorithmic bytes 2 * 16 * sizeof(double) per lattice update
-                and the step time measured with HIP events on the stream the
-                kernel runs on; `traffic` = measured HBM bytes per launch
-                from the committed hardware-counter summary when it was
-                taken on the current kernel source (else null);
-  fp32          the FP32 forms (FP32 arithmetic; FP32 storage with FP64
-                arithmetic) on the same grid;
-  grid_4096     FP64 and FP32 at 4096^2, a working set far above the 256 MB
-                last-level cache (the grid for roofline claims);
-  riemann4096   four-quadrant Riemann configuration 3, 4096^2, outflow, Sensor A
-                (the Ducros gate of Sensor B loses admissibility at this grid):
-                per-step rates, and the whole FP32 run to t = 0.25;
-  d1q2          the D1Q2 step (Sod shock tube data) at 2^26 cells;
+  roofline      the fused step kernel against the 8 TB/s HBM peak: algorithmic
+                bytes 2 * 16 * 4 per lattice update over the step time measured
+                with HIP events on the library's stream; `traffic` = measured
+                HBM bytes per launch from the committed hardware-counter summary
+                when it was taken on the current kernel source (else null);
+  c3            the Riemann configurations at 4096^2: configuration 12 (Sensor B)
+                in FP64 and FP32 storage with FP64 arithmetic, configuration 3
+                (interacting shocks, Sensor A: under Sensor B it loses
+                admissibility from 800^2 up) in all three forms, and whole runs
+                to t = 0.25 timed by the host clock (batches and their host
+                read-backs included);
+  c1_sod        the Sod tube, 1000 cells, whole run to t = 0.2 (launch-bound);
+  c2_vortex     the isentropic vortex at 1024^2 (all forms) and 4096^2;
+  c4_bzt        the dense-gas tube, 8192 cells, whole runs (launch-bound), and
+                its 2-D extrusion at 2048^2 (all forms, shifted energy gauge in
+                FP32), per step and whole run to t = 0.2;
+  d1q2          the D1Q2 step (Sod data) at 2^26 cells;
   adjoint       adjoint/forward step-cost ratio on the adjoint workload
                 (1024^2 perturbed vortex, frozen dt = 1/625, Sensor B), per
                 step and end to end (checkpointed forward + backward);
-  cpu_baseline  the FP64 CPU oracle (OpenMP) on a bounded sample of the
-                headline workload.
+  copy          plain device copies of one 4096^2 FP64 population array and a
+                read-only stream: the attainable bandwidth;
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the headline
+                workload, on all host threads and on one.
 """
 import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -39,9 +48,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "d2q4_fp64_vortex1024_traffic.txt")
-KERNEL_SOURCES = ("paper_2609_10639_amd/csrc/vlbm_step2d.hip", "paper_2609_10639_amd/csrc/vlbm_common.hpp",
-                  "paper_2609_10639_amd/csrc/vlbm_api.cpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "d2q4_fp32_riemann12_4096_traffic.txt")
+KERNEL_SOURCES = ("paper_2609_10639_amd/csrc/vlbm_step2d.hip", "paper_2609_10639_amd/csrc/vlbm_planes.hpp",
+                  "paper_2609_10639_amd/csrc/vlbm_common.hpp", "paper_2609_10639_amd/csrc/vlbm_api.cpp")
+WORKLOAD = ("four-quadrant Riemann problem, configuration 12, [0,1]^2, outflow, ideal gas gamma 1.4, D2Q4, "
+            "Sensor B (0.7, 1, 16), CFL 0.45 retargeted every step, FP32 populations and arithmetic")
 
 
 def parse():
@@ -49,51 +60,33 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--grid", type=int, default=1024)
-    ap.add_argument("--big-grid", type=int, default=4096)
+    ap.add_argument("--grid", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline measurement only")
-    ap.add_argument("--cpu-steps", type=int, default=500)   # about 10 s of host time on 16 threads
-    ap.add_argument("--only", default="", help="profiling aid: fp64 | fp32 | fp32_mixed | big64 | big32 | "
-                                                "riemann32 | d1q2_64 | d1q2_32 | adjoint32 | adjoint64 | copy")
+    ap.add_argument("--cpu-steps", type=int, default=20, help="oracle steps of the all-thread sample")
+    ap.add_argument("--cpu-steps-1t", type=int, default=2, help="oracle steps of the one-thread sample")
+    ap.add_argument("--only", default="", help="profiling aid: one measurement, e.g. headline | r12_fp64 | "
+                                                "r3_fp32 | vortex1024_fp32 | bzt2048_fp32 | d1q2_fp32 | "
+                                                "adjoint32 | copy")
     return ap.parse_args()
 
 
 # ------------------------------------------------------------------ workloads
+
+def riemann_cfg(n, config):
+    """Configuration 12 with Sensor B, or configuration 3 with Sensor A (the
+    Ducros gate of Sensor B loses admissibility on it from 800^2 up)."""
+    from paper_2609_10639_amd import problems as pr
+    W0, dx = pr.riemann2d(n, config)
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2 if config == 12 else 1,
+                    **pr.SENSOR_2D, **pr.IDEAL_AIR.config())
+
 
 def vortex_cfg(n):
     from paper_2609_10639_amd import problems as pr
     W0, dx = pr.vortex(n)
     return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D,
                     **pr.IDEAL_AIR.config())
-
-
-def riemann_cfg(n):
-    """Configuration 3 with Sensor A (0.7, 1, 16): with the Ducros gate of
-    Sensor B it loses admissibility on grids from 800^2 up."""
-    from paper_2609_10639_amd import problems as pr
-    W0, dx = pr.riemann2d(n, 3)
-    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=1, **pr.SENSOR_2D,
-                    **pr.IDEAL_AIR.config())
-
-
-def whole_run(W0, cfg, precision, t_end):
-    """One run from W0 to t_end (every step retargeted, landing exactly), timed
-    by the host clock around run_to_time: the whole-job rate, batches and their
-    host read-backs included."""
-    import torch
-    from paper_2609_10639_amd import Solver
-    s = Solver(precision=precision, **cfg)
-    s.init(W0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    n = s.run_to_time(t_end)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert s.clock()[0] == t_end
-    s.close()
-    cells = cfg["nx"] * cfg["ny"]
-    return {"t_end": t_end, "steps": n, "seconds": round(dt, 3), "MLUPS": round(n * cells / dt / 1e6, 1)}
 
 
 def sod_cfg(n):
@@ -103,11 +96,36 @@ def sod_cfg(n):
                     **pr.IDEAL_AIR.config())
 
 
+def energy_gauge(W0):
+    """Mean specific internal energy of W0 (the e_offset of the FP32 dense-gas runs)."""
+    D = W0.shape[0] - 2
+    ke = 0.5 * sum(W0[1 + a] ** 2 for a in range(D)) / W0[0]
+    return float(((W0[D + 1] - ke) / W0[0]).mean())
+
+
+def bzt_cfg(n, dim):
+    from paper_2609_10639_amd import problems as pr
+    if dim == 1:
+        W0, dx = pr.bzt_tube(n)
+        cfg = dict(dim=1, nx=n, ny=1, dx=dx, bc=(1, 1, 1, 1), cfl=0.5, sensor=1, **pr.SENSOR_1D)
+    else:
+        W0, dx = pr.bzt_extrusion(n)
+        cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D)
+    return W0, dict(cfg, **pr.VDW_REDUCED_CV50.config())
+
+
 def adjoint_cfg(n=1024, steps=625):
     from paper_2609_10639_amd import problems as pr
     W0, dx = pr.vortex_perturbed(n, amplitude=1e-3, seed=42)
     return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), retarget_every=0, c_fixed=dx * steps, sensor=2,
                     **pr.SENSOR_2D, **pr.IDEAL_AIR.config())
+
+
+def with_gauge(W0, cfg, precision):
+    """FP32 dense-gas runs store the energy in the shifted gauge."""
+    if cfg.get("eos", 0) == 1 and precision != "fp64":
+        return dict(cfg, e_offset=energy_gauge(W0))
+    return cfg
 
 
 # ------------------------------------------------------------------ timing
@@ -122,7 +140,7 @@ def time_steps(W0, cfg, precision, steps, warmup):
     library's stream, synchronised on both sides.  Returns ms per step."""
     import torch
     from paper_2609_10639_amd import Solver
-    s = Solver(precision=precision, **cfg)
+    s = Solver(precision=precision, **with_gauge(W0, cfg, precision))
     s.init(W0)
     if warmup:
         s.step(warmup)
@@ -135,6 +153,25 @@ def time_steps(W0, cfg, precision, steps, warmup):
     assert done == steps, (done, steps)
     s.close()
     return e0.elapsed_time(e1) / steps
+
+
+def whole_run(W0, cfg, precision, t_end):
+    """One run from W0 to t_end (every step retargeted, landing exactly), timed
+    by the host clock around run_to_time: the whole-job rate, batches and their
+    host read-backs included."""
+    import torch
+    from paper_2609_10639_amd import Solver
+    s = Solver(precision=precision, **with_gauge(W0, cfg, precision))
+    s.init(W0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = s.run_to_time(t_end)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert s.clock()[0] == t_end
+    s.close()
+    cells = cfg["nx"] * cfg["ny"]
+    return {"t_end": t_end, "steps": n, "seconds": round(dt, 4), "MLUPS": round(n * cells / dt / 1e6, 1)}
 
 
 def bytes_per_lu(dim, precision):
@@ -151,14 +188,14 @@ def kernel_source_hash():
 
 
 def measured_traffic(cells):
-    """HBM bytes per launch of the FP64 step at `cells`, from the committed
-    counter summary, if it was taken on the current kernel source."""
+    """HBM bytes per launch of the headline step, from the committed counter
+    summary, if it was taken on the current kernel source and grid."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as fh:
-            for line in fh:
-                if ":" in line and not line.startswith("#"):
-                    k, v = line.split(":", 1)
+            for ln in fh:
+                if ":" in ln and not ln.startswith("#"):
+                    k, v = ln.split(":", 1)
                     kv[k.strip()] = v.strip()
         if kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv.get("cells", -1)) != cells:
             return None
@@ -176,6 +213,11 @@ def roofline(ms, cells, dim, precision, traffic=None):
 def line(ms, cells, dim, precision):
     return {"MLUPS": round(cells / ms / 1e3, 1), "ms_per_step": round(ms, 5),
             "roofline": roofline(ms, cells, dim, precision)}
+
+
+def per_step(W0, cfg, precisions, steps, warmup):
+    cells = cfg["nx"] * cfg["ny"]
+    return {p: line(time_steps(W0, cfg, p, steps, warmup), cells, cfg["dim"], p) for p in precisions}
 
 
 def adjoint_ratio(precision, n=1024, nsteps=625, reps=50):
@@ -245,31 +287,72 @@ def adjoint_ratio(precision, n=1024, nsteps=625, reps=50):
             "adj_ms_per_step": round(t_adj, 5), "step_ratio": round(t_adj / t_fwd, 3), **e2e}
 
 
-def cpu_baseline(n, steps):
-    from oracle import core
-    W0, cfg = vortex_cfg(n)
-    o = core.Oracle(**cfg)
-    o.init(W0)
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ORACLE_SAMPLE = """
+import json, sys, time
+sys.path.insert(0, %r)
+from bench import riemann_cfg
+from oracle import core
+n, steps = %d, %d
+W0, cfg = riemann_cfg(n, 12)
+o = core.Oracle(**cfg)
+o.init(W0)
+o.step()
+t0 = time.perf_counter()
+for _ in range(steps):
     o.step()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        o.step()
-    dt = time.perf_counter() - t0
-    return {"value": round(n * n * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": core.threads(),
-            "kind": "oracle", "sample": "%d FP64 steps of the %dx%d vortex (%.1f s, OpenMP)" % (steps, n, n, dt)}
+dt = time.perf_counter() - t0
+print(json.dumps({"seconds": dt, "steps": steps, "threads": core.threads()}))
+"""
+
+
+def oracle_sample(n, steps, threads=None):
+    """The FP64 oracle on `steps` steps of the headline workload (after one
+    untimed step), in a child process so that its OpenMP thread count can be
+    set; returns the timing record."""
+    env = dict(os.environ)
+    if threads:
+        env["OMP_NUM_THREADS"] = str(threads)
+    out = subprocess.run([sys.executable, "-c", _ORACLE_SAMPLE % (ROOT, n, steps)], env=env, capture_output=True,
+                         text=True, check=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(n, steps_all, steps_one):
+    allt = oracle_sample(n, steps_all)
+    one = oracle_sample(n, steps_one, threads=1)
+    cells = n * n
+    rate = lambda r: round(cells * r["steps"] / r["seconds"] / 1e6, 2)
+    return {"value": rate(allt), "unit": "MLUPS", "cores": allt["threads"], "kind": "oracle",
+            "sample": "%d FP64 oracle steps of the headline workload at %dx%d (%.1f s, %d OpenMP threads)" % (
+                steps_all, n, n, allt["seconds"], allt["threads"]),
+            "one_thread": {"value": rate(one), "unit": "MLUPS", "cores": 1,
+                           "sample": "%d steps (%.1f s)" % (steps_one, one["seconds"])},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "build": "gcc -O3 -ffp-contract=off -fopenmp, FP64"}
 
 
 def copy_bw(nbytes, steps, warmup):
-    """Plain device copies of `nbytes`: torch's copy_ and the library's probe
-    (16-byte non-temporal loads and stores): attainable bandwidth, and the
-    reference for the hardware byte counters (torch's copy)."""
+    """Plain device copies of `nbytes` (torch's copy_, the library's copy probe)
+    and the probe's read-only stream: attainable bandwidth, and the reference
+    for the hardware byte counters."""
     import torch
     from paper_2609_10639_amd import _native
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     stream = torch.cuda.current_stream().cuda_stream
 
-    def timed(fn):
+    def timed(fn, moved):
         for _ in range(warmup):
             fn()
         e0, e1 = _events()
@@ -279,32 +362,34 @@ def copy_bw(nbytes, steps, warmup):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        return {"ms": round(ms, 5), "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+        return {"ms": round(ms, 5), "GBs": round(moved / (ms * 1e-3) / 1e9, 1)}
 
-    torch_copy = timed(lambda: dst.copy_(src))
+    torch_copy = timed(lambda: dst.copy_(src), 2 * nbytes)
     dst.zero_()
-    probe = timed(lambda: _native.copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, stream))
+    probe = timed(lambda: _native.copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, stream, 0), 2 * nbytes)
     ok = bool(torch.equal(src, dst))
-    return {"bytes_read": nbytes, "bytes_written": nbytes, "torch_copy": torch_copy, "probe": probe,
-            "probe_copied_exactly": ok}
+    read = timed(lambda: _native.copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, stream, 1), nbytes)
+    return {"bytes": nbytes, "torch_copy": torch_copy, "probe_copy": probe, "probe_copied_exactly": ok,
+            "probe_read_only": read}
 
 
 # ------------------------------------------------------------------ main
 
 def only(a):
     o = a.only
+    n = a.grid
     if o == "copy":
-        return dict(only=o, **copy_bw(16 * a.big_grid * a.big_grid * 8, a.steps, a.warmup))
+        return dict(only=o, **copy_bw(16 * n * n * 8, a.steps, a.warmup))
     if o.startswith("adjoint"):
         return dict(only=o, **adjoint_ratio("fp32" if o.endswith("32") else "fp64"))
-    prec = {"fp64": "fp64", "fp32": "fp32", "fp32_mixed": "fp32_mixed", "big64": "fp64", "big32": "fp32",
-            "riemann32": "fp32", "d1q2_64": "fp64", "d1q2_32": "fp32"}[o]
-    if o.startswith("d1q2"):
-        W0, cfg = sod_cfg(1 << 26)
-    elif o == "riemann32":
-        W0, cfg = riemann_cfg(a.big_grid)
+    if o == "headline":
+        W0, cfg, prec = *riemann_cfg(n, 12), "fp32"
     else:
-        W0, cfg = vortex_cfg(a.big_grid if o.startswith("big") else a.grid)
+        name, prec = o.rsplit("_", 1)
+        prec = {"fp64": "fp64", "fp32": "fp32", "mixed": "fp32_mixed"}[prec]
+        W0, cfg = {"r12": lambda: riemann_cfg(n, 12), "r3": lambda: riemann_cfg(n, 3),
+                   "vortex1024": lambda: vortex_cfg(1024), "vortex4096": lambda: vortex_cfg(4096),
+                   "bzt2048": lambda: bzt_cfg(2048, 2), "d1q2": lambda: sod_cfg(1 << 26)}[name]()
     ms = time_steps(W0, cfg, prec, a.steps, a.warmup)
     return dict(only=o, grid=[cfg["ny"], cfg["nx"]], **line(ms, cfg["nx"] * cfg["ny"], cfg["dim"], prec))
 
@@ -320,48 +405,58 @@ def main():
         print(json.dumps(only(a)), flush=True)
         return
 
-    W0, cfg = vortex_cfg(a.grid)
-    cells = a.grid * a.grid
-    ms64 = time_steps(W0, cfg, "fp64", a.steps, a.warmup)
+    n = a.grid
+    cells = n * n
+    W0, cfg = riemann_cfg(n, 12)
+    ms = time_steps(W0, cfg, "fp32", a.steps, a.warmup)
     out = {
         "metric": "MLUPS and % of HBM roofline (FP64 vs FP32), adjoint/forward step-cost ratio",
-        "value": round(cells / ms64 / 1e3, 1),
+        "value": round(cells / ms / 1e3, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms64, 5),
+        "ms_per_step": round(ms, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "isentropic vortex advection, periodic [0,10]^2, strength 5, background (1,1), "
-                               "ideal gas 1.4, D2Q4, Sensor B, CFL 0.45", "grid": [a.grid, a.grid], "cells": cells},
-        "roofline": roofline(ms64, cells, 2, "fp64", measured_traffic(cells)),
+        "config": {"workload": WORKLOAD, "grid": [n, n], "cells": cells},
+        "roofline": roofline(ms, cells, 2, "fp32", measured_traffic(cells)),
     }
     if not a.no_extra:
-        out["fp32"] = {p: line(time_steps(W0, cfg, p, a.steps, a.warmup), cells, 2, p)
-                       for p in ("fp32", "fp32_mixed")}
-        nb = a.big_grid
-        Wb, cb = vortex_cfg(nb)
-        ksteps = max(20, a.steps // 4)
-        out["grid_%d" % nb] = {p: line(time_steps(Wb, cb, p, ksteps, 5), nb * nb, 2, p)
-                               for p in ("fp64", "fp32", "fp32_mixed")}
+        k = max(20, a.steps // 4)
+        c3 = {"config12_sensorB": per_step(W0, cfg, ("fp64", "fp32_mixed"), k, 5)}
+        c3["config12_sensorB"]["fp32_to_t_end"] = whole_run(W0, cfg, "fp32", 0.25)
+        c3["config12_sensorB"]["fp64_to_t_end"] = whole_run(W0, cfg, "fp64", 0.25)
+        del W0
+        W3, cf3 = riemann_cfg(n, 3)
+        c3["config3_sensorA"] = per_step(W3, cf3, ("fp32", "fp64", "fp32_mixed"), k, 5)
+        c3["config3_sensorA"]["fp32_to_t_end"] = whole_run(W3, cf3, "fp32", 0.25)
+        del W3
+        out["c3"] = c3
+        Ws, cs = sod_cfg(1000)
+        out["c1_sod"] = {"launch_bound": True, "fp64_to_t_end": whole_run(Ws, cs, "fp64", 0.2)}
+        Wv, cv = vortex_cfg(1024)
+        out["c2_vortex"] = {"1024": per_step(Wv, cv, ("fp64", "fp32", "fp32_mixed"), a.steps, a.warmup)}
+        Wv, cv = vortex_cfg(4096)
+        out["c2_vortex"]["4096"] = per_step(Wv, cv, ("fp64", "fp32"), k, 5)
+        del Wv
+        Wt, ct = bzt_cfg(8192, 1)
+        Wb, cb = bzt_cfg(2048, 2)
+        out["c4_bzt"] = {"1d_8192": {"launch_bound": True, **{p + "_to_t_end": whole_run(Wt, ct, p, 0.2)
+                                                              for p in ("fp64", "fp32")}},
+                         "2d_2048": per_step(Wb, cb, ("fp64", "fp32", "fp32_mixed"), a.steps, a.warmup)}
+        out["c4_bzt"]["2d_2048"]["fp32_to_t_end"] = whole_run(Wb, cb, "fp32", 0.2)
         del Wb
-        Wr, cr = riemann_cfg(nb)
-        out["riemann%d" % nb] = {p: line(time_steps(Wr, cr, p, ksteps, 5), nb * nb, 2, p) for p in ("fp32", "fp64")}
-        out["riemann%d" % nb]["fp32_to_t_end"] = whole_run(Wr, cr, "fp32", 0.25)
-        del Wr
         W1, c1 = sod_cfg(1 << 26)
-        out["d1q2"] = {"cells": 1 << 26, **{p: line(time_steps(W1, c1, p, ksteps, 5), 1 << 26, 1, p)
-                                            for p in ("fp64", "fp32")}}
+        out["d1q2"] = {"cells": 1 << 26, **per_step(W1, c1, ("fp64", "fp32"), k, 5)}
         del W1
         out["adjoint"] = [adjoint_ratio("fp32"), adjoint_ratio("fp64")]
-        # context for the roofline fractions: a plain device copy of one 4096^2 FP64 population array
-        out["copy"] = copy_bw(16 * nb * nb * 8, 20, 3)
+        out["copy"] = copy_bw(16 * n * n * 8, 20, 3)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.grid, a.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(n, a.cpu_steps, a.cpu_steps_1t)
     print(json.dumps(out), flush=True)
 
 

@@ -34,7 +34,10 @@
  *   - a sensor normaliser max|Q_alpha,k| equal to 0 gives s_hat_k = 0;
  *   - outflow is an edge-replicated ghost cell: streaming sources, central
  *     differences and the box filter clamp their neighbour index;
- *   - with retarget_every = K > 1 a retarget is forced when s_max > c.
+ *   - with retarget_every = K > 1 a retarget is forced when s_max > c;
+ *   - the Ducros ratio (Eq. 33) takes dilatation and vorticity in lattice
+ *     units (dt = dx/c times their central differences), so that its
+ *     regulariser eps_theta is dimensionless.
  */
 #ifndef VLBM_H
 #define VLBM_H
@@ -105,6 +108,10 @@ typedef struct {
     void* stream;            /* hipStream_t, or NULL for the default stream */
 } vlbm_config;
 
+/* Validate a configuration without touching the device: VLBM_OK if
+ * vlbm_create would accept it, VLBM_EINVAL otherwise (the same checks). */
+vlbm_status vlbm_check_config(const vlbm_config* cfg);
+
 /* Validate the configuration, allocate two population buffers, the clock and
  * reduction ring and scratch on the current device.  Ownership of *out passes
  * to the caller (release with vlbm_destroy).  EINVAL on a bad config, ENOMEM
@@ -148,12 +155,17 @@ vlbm_status vlbm_get_f(vlbm_ctx* ctx, void* out, int32_t out_on_device);
 /* Current time, link speed c and step count (synchronises). */
 vlbm_status vlbm_get_clock(vlbm_ctx* ctx, double* t, double* c, int64_t* n);
 
-/* Checkpoint / resume: the state is the populations plus (t, c, n) and the
- * reductions of the current state.  `buf` is a device buffer of at least
- * vlbm_state_bytes() bytes.  restore(save(x)) resumes bitwise. */
+/* Checkpoint / resume (no counterpart in the paper: a service of the library).
+ * The state is the populations plus (t, c, n) and the reductions of the
+ * current state, behind a 64-byte header naming the lattice, grid, precision
+ * and plane layout of the context that saved it.  `buf` is a device buffer of
+ * `bytes` >= vlbm_state_bytes() bytes, owned by the caller.  vlbm_restore
+ * returns VLBM_EINVAL, leaving the context unchanged, when the buffer is too
+ * small, when its header does not match the context or when its clock is not
+ * valid.  Both synchronise the stream.  restore(save(x)) resumes bitwise. */
 size_t vlbm_state_bytes(const vlbm_ctx* ctx);
-vlbm_status vlbm_save(vlbm_ctx* ctx, void* buf);
-vlbm_status vlbm_restore(vlbm_ctx* ctx, const void* buf);
+vlbm_status vlbm_save(vlbm_ctx* ctx, void* buf, size_t bytes);
+vlbm_status vlbm_restore(vlbm_ctx* ctx, const void* buf, size_t bytes);
 
 /* Elements per population plane (padding included) and bytes of one
  * population array (2*dim*(dim+2) planes) in the context's precision; the
@@ -204,15 +216,20 @@ vlbm_status vlbm_raw_moments_adjoint(vlbm_ctx* ctx, const double* Wbar, void* la
 /* Message of the last failing call on this context (valid until the next call). */
 const char* vlbm_last_error(const vlbm_ctx* ctx);
 
-/* Measurement aid, not part of the method: copies `bytes` (a multiple of 16)
- * from the device buffer src to the device buffer dst, which must not overlap,
- * with a grid-stride kernel of 16-byte non-temporal loads and stores: the
- * attainable-bandwidth reference that roofline fractions are read against.
+/* Measurement aid, not part of the method: the attainable-bandwidth references
+ * that roofline fractions are read against.  mode 0 copies `bytes` (a multiple
+ * of 16) from the device buffer src to the device buffer dst, which must not
+ * overlap, with a grid-stride kernel of 16-byte non-temporal loads and stores.
+ * mode 1 only reads src (four independent 16-byte loads in flight per lane)
+ * and writes one 16-byte XOR of the words each workgroup read to dst:
+ * vlbm_copy_probe_read_bytes(bytes) bytes (at most 128 KiB), which dst must
+ * hold; the XOR of those words is the XOR of all 16-byte words of src.
  * Stream-ordered on `stream` (a hipStream_t; NULL: the null stream), returns
- * before the copy completes; the caller owns both buffers.  VLBM_EINVAL for a
- * null pointer or a size that is not a multiple of 16, VLBM_EDEVICE if the
- * launch fails. */
-vlbm_status vlbm_copy_probe(const void* src, void* dst, size_t bytes, void* stream);
+ * before the kernel completes; the caller owns both buffers.  VLBM_EINVAL for a
+ * null pointer, a size that is not a multiple of 16 or an unknown mode,
+ * VLBM_EDEVICE if the launch fails. */
+vlbm_status vlbm_copy_probe(const void* src, void* dst, size_t bytes, void* stream, int32_t mode);
+size_t vlbm_copy_probe_read_bytes(size_t bytes);
 
 #ifdef __cplusplus
 }

@@ -49,7 +49,7 @@ def build(force=False):
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+    cmd = ["gcc", "-O3", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB)

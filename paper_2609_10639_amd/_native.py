@@ -58,6 +58,7 @@ _lib = None
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 _SIGS = [
+    ("vlbm_check_config", ctypes.c_int, [ctypes.POINTER(VlbmConfig)]),
     ("vlbm_create", ctypes.c_int, [ctypes.POINTER(VlbmConfig), ctypes.POINTER(ctypes.c_void_p)]),
     ("vlbm_destroy", None, [_P]),
     ("vlbm_init", ctypes.c_int, [_P, _P, ctypes.c_int32]),
@@ -69,8 +70,8 @@ _SIGS = [
     ("vlbm_get_f", ctypes.c_int, [_P, _P, ctypes.c_int32]),
     ("vlbm_get_clock", ctypes.c_int, [_P, _D, _D, ctypes.POINTER(ctypes.c_int64)]),
     ("vlbm_state_bytes", ctypes.c_size_t, [_P]),
-    ("vlbm_save", ctypes.c_int, [_P, _P]),
-    ("vlbm_restore", ctypes.c_int, [_P, _P]),
+    ("vlbm_save", ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    ("vlbm_restore", ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     ("vlbm_plane_elems", ctypes.c_int64, [_P]),
     ("vlbm_population_bytes", ctypes.c_size_t, [_P]),
     ("vlbm_raw_init", ctypes.c_int, [_P, _P, _P, _P]),
@@ -80,7 +81,8 @@ _SIGS = [
     ("vlbm_raw_moments", ctypes.c_int, [_P, _P, _P]),
     ("vlbm_raw_moments_adjoint", ctypes.c_int, [_P, _P, _P]),
     ("vlbm_last_error", ctypes.c_char_p, [_P]),
-    ("vlbm_copy_probe", ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    ("vlbm_copy_probe", ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, ctypes.c_int32]),
+    ("vlbm_copy_probe_read_bytes", ctypes.c_size_t, [ctypes.c_size_t]),
 ]
 EXPORTED = [name for name, _, _ in _SIGS]
 
@@ -107,7 +109,8 @@ def check(status, handle=None):
         raise VlbmError(status, msg)
 
 
-def copy_probe(src, dst, nbytes, stream):
-    """vlbm_copy_probe: device-to-device copy of nbytes through the library's
-    bandwidth probe kernel (a measurement aid), stream-ordered."""
-    check(lib().vlbm_copy_probe(src, dst, nbytes, stream))
+def copy_probe(src, dst, nbytes, stream, mode=0):
+    """vlbm_copy_probe: device-to-device copy of nbytes (mode 0), or a read-only
+    stream over src folded into per-workgroup XOR words in dst (mode 1), through
+    the library's bandwidth probe kernels (a measurement aid), stream-ordered."""
+    check(lib().vlbm_copy_probe(src, dst, nbytes, stream, mode))

@@ -234,12 +234,14 @@ bool check_config(const vlbm_config* c, std::string& why)
         return why = "bad precision", false;
     if (c->dim == 2) {
         // the D2Q4 marches address four planes from one buffer resource with
-        // 32-bit offsets: 4 padded planes must fit in 4 GiB (2^27 cells in FP64,
-        // 2^28 with FP32 storage)
+        // 32-bit offsets: 4 padded planes must fit in 4 GiB.  A plane holds the
+        // cells rounded up to 64 plus 1 KB, so the largest grids are 2^27 - 128
+        // cells in FP64 and 2^28 - 256 with FP32 storage
         const long long esize = c->precision == VLBM_FP64 ? 8 : 4;
         const long long plane = padded_plane(c->nx * c->ny, esize);
         if (4 * plane * esize > (1LL << 32))
-            return why = "grid too large for the D2Q4 kernels' 32-bit offsets (2^27 cells in FP64, 2^28 with FP32 storage)",
+            return why = "grid too large for the D2Q4 kernels' 32-bit offsets (at most 2^27 - 128 cells in FP64, "
+                         "2^28 - 256 with FP32 storage)",
                    false;
     }
     return true;
@@ -248,6 +250,12 @@ bool check_config(const vlbm_config* c, std::string& why)
 }  // namespace
 
 extern "C" {
+
+vlbm_status vlbm_check_config(const vlbm_config* cfg)
+{
+    std::string why;
+    return cfg && check_config(cfg, why) ? VLBM_OK : VLBM_EINVAL;
+}
 
 vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
 {
@@ -537,45 +545,86 @@ vlbm_status vlbm_get_clock(vlbm_ctx* ctx, double* t, double* c, int64_t* n)
     return VLBM_OK;
 }
 
+// Checkpoint layout: a header naming the context it was taken from, the
+// populations, the ring slot of the current state (clock and reductions), the
+// step count.
+struct CkptHeader {
+    char magic[8];
+    int64_t version, dim, nx, ny, precision, plane, nplanes;
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header is 64 bytes");
+constexpr int64_t kCkptVersion = 1;
+
+static CkptHeader ckpt_header(const vlbm_ctx* ctx)
+{
+    CkptHeader h{};
+    memcpy(h.magic, "VLBMCKPT", 8);
+    h.version = kCkptVersion;
+    h.dim = ctx->D;
+    h.nx = ctx->cfg.nx;
+    h.ny = ctx->cfg.ny;
+    h.precision = ctx->cfg.precision;
+    h.plane = ctx->plane;
+    h.nplanes = ctx->nplanes;
+    return h;
+}
+
 size_t vlbm_state_bytes(const vlbm_ctx* ctx)
 {
     if (!ctx) return 0;
-    return (size_t)ctx->nplanes * ctx->plane * ctx->esize + (kSlot + 8) * sizeof(double);
+    return sizeof(CkptHeader) + (size_t)ctx->nplanes * ctx->plane * ctx->esize + (kSlot + 8) * sizeof(double);
 }
 
-vlbm_status vlbm_save(vlbm_ctx* ctx, void* buf)
+vlbm_status vlbm_save(vlbm_ctx* ctx, void* buf, size_t bytes)
 {
     if (!ctx || !buf) return fail(ctx, VLBM_EINVAL, "null argument");
     if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
-    const size_t fb = (size_t)ctx->nplanes * ctx->plane * ctx->esize;
-    HIPCHK(ctx, hipMemcpyAsync(buf, ctx->f[ctx->n & 1], fb, hipMemcpyDeviceToDevice, ctx->stream));
-    // the current slot (clock + reductions of the state) and the step count
-    HIPCHK(ctx, hipMemcpyAsync((char*)buf + fb, ctx->ring + kSlot * (ctx->n % 3), kSlot * sizeof(double),
+    if (bytes < vlbm_state_bytes(ctx)) return fail(ctx, VLBM_EINVAL, "checkpoint buffer smaller than vlbm_state_bytes");
+    const size_t hb = sizeof(CkptHeader), fb = (size_t)ctx->nplanes * ctx->plane * ctx->esize;
+    char* b = (char*)buf;
+    // header and step count staged in pinned host memory
+    double* stage = ctx->host + kHostAux;
+    const CkptHeader h = ckpt_header(ctx);
+    memcpy(stage, &h, hb);
+    stage[hb / sizeof(double)] = (double)ctx->n;
+    HIPCHK(ctx, hipMemcpyAsync(b, stage, hb, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(b + hb, ctx->f[ctx->n & 1], fb, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(b + hb + fb, ctx->ring + kSlot * (ctx->n % 3), kSlot * sizeof(double),
                                hipMemcpyDeviceToDevice, ctx->stream));
-    ctx->host[kHostAux] = (double)ctx->n;
-    HIPCHK(ctx, hipMemcpyAsync((char*)buf + fb + kSlot * sizeof(double), ctx->host + kHostAux, sizeof(double),
+    HIPCHK(ctx, hipMemcpyAsync(b + hb + fb + kSlot * sizeof(double), stage + hb / sizeof(double), sizeof(double),
                                hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return VLBM_OK;
 }
 
-vlbm_status vlbm_restore(vlbm_ctx* ctx, const void* buf)
+vlbm_status vlbm_restore(vlbm_ctx* ctx, const void* buf, size_t bytes)
 {
     if (!ctx || !buf) return fail(ctx, VLBM_EINVAL, "null argument");
-    const size_t fb = (size_t)ctx->nplanes * ctx->plane * ctx->esize;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->host + kHostAux, (const char*)buf + fb, (kSlot + 1) * sizeof(double),
-                               hipMemcpyDeviceToHost, ctx->stream));
+    if (bytes < vlbm_state_bytes(ctx)) return fail(ctx, VLBM_EINVAL, "checkpoint buffer smaller than vlbm_state_bytes");
+    const size_t hb = sizeof(CkptHeader), fb = (size_t)ctx->nplanes * ctx->plane * ctx->esize;
+    const char* b = (const char*)buf;
+    double* stage = ctx->host + kHostAux;
+    HIPCHK(ctx, hipMemcpyAsync(stage, b, hb, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    const long long n = (long long)ctx->host[kHostAux + kSlot];
-    if (n < 0) return fail(ctx, VLBM_EINVAL, "corrupt checkpoint");
+    CkptHeader h;
+    memcpy(&h, stage, hb);
+    const CkptHeader want = ckpt_header(ctx);
+    if (memcmp(&h, &want, hb) != 0)
+        return fail(ctx, VLBM_EINVAL, "checkpoint taken from a context of another grid, lattice or precision");
+    HIPCHK(ctx, hipMemcpyAsync(stage, b + hb + fb, (kSlot + 1) * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const double t = stage[0], c = stage[1], nd = stage[kSlot];
+    if (!(nd >= 0) || nd != std::floor(nd) || !std::isfinite(t) || !(c > 0) || !std::isfinite(c))
+        return fail(ctx, VLBM_EINVAL, "corrupt checkpoint");
+    const long long n = (long long)nd;
     HIPCHK(ctx, launch_reset_ctl(ctx->ring, ctx->stop_at, ctx->err, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->f[n & 1], buf, fb, hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->ring + kSlot * (n % 3), (const char*)buf + fb, kSlot * sizeof(double),
+    HIPCHK(ctx, hipMemcpyAsync(ctx->f[n & 1], b + hb, fb, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->ring + kSlot * (n % 3), b + hb + fb, kSlot * sizeof(double),
                                hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->n = n;
-    ctx->t = ctx->host[kHostAux];
-    ctx->c = ctx->host[kHostAux + 1];
+    ctx->t = t;
+    ctx->c = c;
     ctx->initialised = true;
     return VLBM_OK;
 }
@@ -674,10 +723,12 @@ vlbm_status vlbm_raw_moments_adjoint(vlbm_ctx* ctx, const double* Wbar, void* la
 
 const char* vlbm_last_error(const vlbm_ctx* ctx) { return ctx ? ctx->msg.c_str() : "null context"; }
 
-vlbm_status vlbm_copy_probe(const void* src, void* dst, size_t bytes, void* stream)
+vlbm_status vlbm_copy_probe(const void* src, void* dst, size_t bytes, void* stream, int32_t mode)
 {
-    if (!src || !dst || bytes % 16 != 0) return VLBM_EINVAL;
-    return launch_copy_probe(src, dst, bytes, (hipStream_t)stream) == hipSuccess ? VLBM_OK : VLBM_EDEVICE;
+    if (!src || !dst || bytes % 16 != 0 || (mode != 0 && mode != 1)) return VLBM_EINVAL;
+    return launch_copy_probe(src, dst, bytes, mode, (hipStream_t)stream) == hipSuccess ? VLBM_OK : VLBM_EDEVICE;
 }
+
+size_t vlbm_copy_probe_read_bytes(size_t bytes) { return read_probe_out_bytes(bytes); }
 
 }  // extern "C"

@@ -331,9 +331,10 @@ hipError_t launch_unpad(int D, long long plane, long long ncell, bool fp32, doub
     return hipGetLastError();
 }
 
-// Measurement aid: grid-stride copy, 16 bytes per lane with non-temporal loads
-// and stores (the fastest plain copy measured on MI355X: 16384 workgroups of
-// 512 threads).
+// Measurement aids.  Copy: grid-stride, 16 bytes per lane with non-temporal
+// loads and stores (the fastest plain copy measured on MI355X: 65536
+// workgroups of 512 threads, 5.7 TB/s; four independent loads in flight per
+// lane measured slower, 5.2 TB/s).
 __global__ void __launch_bounds__(512) k_copy_probe(const double2* __restrict__ a, double2* __restrict__ b, size_t n)
 {
     typedef double d2v __attribute__((ext_vector_type(2)));
@@ -343,11 +344,58 @@ __global__ void __launch_bounds__(512) k_copy_probe(const double2* __restrict__ 
     }
 }
 
-hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t st)
+// Read-only stream: four independent 16-byte non-temporal loads in flight per
+// lane, folded into an XOR per workgroup (the read rate of the memory system
+// without a write stream: 6.2 TB/s measured on MI355X with 8192 workgroups of
+// 256 threads).  Workgroup b writes its 16-byte XOR to b[blockIdx].
+constexpr int kReadBlocks = 8192, kReadThreads = 256;
+__global__ void __launch_bounds__(kReadThreads) k_read_probe(const ulonglong2* __restrict__ a, ulonglong2* __restrict__ b,
+                                                             size_t n)
+{
+    typedef unsigned long long u2v __attribute__((ext_vector_type(2)));
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    u2v acc = {0ull, 0ull};
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += 4 * stride) {
+        u2v v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const size_t j = i + k * stride;
+            v[k] = j < n ? __builtin_nontemporal_load((const u2v*)(a + j)) : u2v{0ull, 0ull};
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc ^= v[k];
+    }
+    __shared__ unsigned long long sh[2][kReadThreads];
+    sh[0][threadIdx.x] = acc.x;
+    sh[1][threadIdx.x] = acc.y;
+    __syncthreads();
+    for (int o = kReadThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sh[0][threadIdx.x] ^= sh[0][threadIdx.x + o];
+            sh[1][threadIdx.x] ^= sh[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) b[blockIdx.x] = make_ulonglong2(sh[0][0], sh[1][0]);
+}
+
+size_t read_probe_out_bytes(size_t bytes)
 {
     const size_t n = bytes / 16;
-    const size_t blocks = std::min<size_t>(16384, (n + 511) / 512);
-    if (blocks == 0) return hipSuccess;
+    return std::min<size_t>(kReadBlocks, (n + kReadThreads - 1) / kReadThreads) * 16;
+}
+
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int mode, hipStream_t st)
+{
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    if (mode == 1) {
+        const size_t blocks = read_probe_out_bytes(bytes) / 16;
+        hipLaunchKernelGGL(k_read_probe, dim3((unsigned)blocks), dim3(kReadThreads), 0, st, (const ulonglong2*)src,
+                           (ulonglong2*)dst, n);
+        return hipGetLastError();
+    }
+    const size_t blocks = std::min<size_t>(65536, (n + 511) / 512);
     hipLaunchKernelGGL(k_copy_probe, dim3((unsigned)blocks), dim3(512), 0, st, (const double2*)src, (double2*)dst, n);
     return hipGetLastError();
 }

@@ -25,7 +25,8 @@ hipError_t launch_moments_adj(int D, long long plane, long long ncell, bool fp32
 int totals_nparts(long long ncell);
 hipError_t launch_totals(int D, long long plane, long long ncell, bool fp32, double e_off, const void* f,
                          double* partials, double* out, hipStream_t st);
-hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t st);
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int mode, hipStream_t st);
+size_t read_probe_out_bytes(size_t bytes);
 hipError_t launch_unpad(int D, long long plane, long long ncell, bool fp32, double e_off, const void* f, void* out,
                         hipStream_t st);
 

@@ -145,11 +145,16 @@ class Solver:
         """Checkpoint into a new uint8 device tensor."""
         torch = _torch()
         buf = torch.empty(self.state_bytes(), dtype=torch.uint8, device="cuda")
-        self._chk(N.lib().vlbm_save(self._h, ctypes.c_void_p(buf.data_ptr())))
+        self._chk(N.lib().vlbm_save(self._h, ctypes.c_void_p(buf.data_ptr()), buf.numel()))
         return buf
 
     def restore(self, buf):
-        self._chk(N.lib().vlbm_restore(self._h, ctypes.c_void_p(buf.data_ptr())))
+        """Resume from a checkpoint of save(): a contiguous uint8 device tensor
+        (the library refuses one taken on another grid, lattice or precision)."""
+        torch = _torch()
+        if not (isinstance(buf, torch.Tensor) and buf.is_cuda and buf.is_contiguous() and buf.dtype == torch.uint8):
+            raise ValueError("restore needs the contiguous uint8 device tensor that save() returned")
+        self._chk(N.lib().vlbm_restore(self._h, ctypes.c_void_p(buf.data_ptr()), buf.numel()))
 
     # ------------------------------------------------------------ raw (frozen link speed)
     def plane_elems(self):
@@ -164,25 +169,45 @@ class Solver:
         torch = _torch()
         return torch.zeros(N.NORMS_LEN, dtype=torch.float64, device="cuda")
 
+    # The raw entry points read and write whole device arrays through plain
+    # pointers: every tensor is checked for device, layout, dtype and size here,
+    # so that a wrong one raises instead of being read past its end.
+    def _pop(self, t):
+        torch = _torch()
+        return _ptr(t, torch.float32 if self.fp32 else torch.float64, self.Q * self.NK * self.plane_elems(),
+                    "populations")
+
+    def _nrm(self, t):
+        return _ptr(t, _torch().float64, N.NORMS_LEN, "norms")
+
+    def _fld(self, t):
+        return _ptr(t, _torch().float64, self.NK * self.shape[0] * self.shape[1], "W")
+
     def raw_init(self, W0, f0, norms0):
-        self._chk(N.lib().vlbm_raw_init(self._h, _ptr(W0), _ptr(f0), _ptr(norms0)))
+        self._chk(N.lib().vlbm_raw_init(self._h, self._fld(W0), self._pop(f0), self._nrm(norms0)))
 
     def raw_step(self, f_in, norms_in, f_out, norms_out):
-        self._chk(N.lib().vlbm_raw_step(self._h, _ptr(f_in), _ptr(norms_in), _ptr(f_out), _ptr(norms_out)))
+        self._chk(N.lib().vlbm_raw_step(self._h, self._pop(f_in), self._nrm(norms_in), self._pop(f_out),
+                                        self._nrm(norms_out)))
 
     def raw_adjoint_step(self, f_n, norms_n, lam_np1, lam_n):
-        self._chk(N.lib().vlbm_raw_adjoint_step(self._h, _ptr(f_n), _ptr(norms_n), _ptr(lam_np1), _ptr(lam_n)))
+        self._chk(N.lib().vlbm_raw_adjoint_step(self._h, self._pop(f_n), self._nrm(norms_n), self._pop(lam_np1),
+                                                self._pop(lam_n)))
 
     def raw_init_adjoint(self, W0, lam0, W0bar):
-        self._chk(N.lib().vlbm_raw_init_adjoint(self._h, _ptr(W0), _ptr(lam0), _ptr(W0bar)))
+        self._chk(N.lib().vlbm_raw_init_adjoint(self._h, self._fld(W0), self._pop(lam0), self._fld(W0bar)))
 
     def raw_moments(self, f, W):
-        self._chk(N.lib().vlbm_raw_moments(self._h, _ptr(f), _ptr(W)))
+        self._chk(N.lib().vlbm_raw_moments(self._h, self._pop(f), self._fld(W)))
 
     def raw_moments_adjoint(self, Wbar, lam):
-        self._chk(N.lib().vlbm_raw_moments_adjoint(self._h, _ptr(Wbar), _ptr(lam)))
+        self._chk(N.lib().vlbm_raw_moments_adjoint(self._h, self._fld(Wbar), self._pop(lam)))
 
 
-def _ptr(t):
-    assert t.is_cuda and t.is_contiguous()
+def _ptr(t, dtype, numel, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s: a contiguous device tensor is needed" % what)
+    if t.dtype != dtype or t.numel() != numel:
+        raise ValueError("%s: expected %d elements of %s, got %d of %s" % (what, numel, dtype, t.numel(), t.dtype))
     return ctypes.c_void_p(t.data_ptr())

@@ -62,7 +62,7 @@ def _config(dim, nx, ny, precision):
     c = _native.VlbmConfig()
     c.dim, c.nx, c.ny, c.dx = dim, nx, ny, 1.0 / nx
     c.eos, c.gamma, c.cfl, c.retarget_every = 0, 1.4, 0.45, 1
-    c.sensor, c.beta_const, c.beta_min, c.beta_max, c.c_sensor, c.eps_theta = 2, 1.0, 0.75, 1.0, 4.0, 1e-12
+    c.sensor, c.beta_const, c.beta_min, c.beta_max, c.c_sensor, c.eps_theta = 2, 1.0, 0.75, 1.0, 4.0, 1e-10
     c.precision = precision
     return c
 
@@ -81,3 +81,20 @@ def test_grids_beyond_32bit_offsets_are_rejected(nx, ny, precision):
     c = _config(2, nx, ny, precision)
     assert lib.vlbm_create(ctypes.byref(c), ctypes.byref(out)) == _native.EINVAL
     assert not out.value
+
+
+@pytest.mark.parametrize("nx,ny,precision,ok", [(9600, 13981, 0, True), (21301, 6301, 0, False),
+                                                (19200, 13981, 1, True), (19200, 13981, 2, True),
+                                                (13081, 20521, 1, False)])
+def test_d2q4_size_cap_boundary(nx, ny, precision, ok):
+    """The largest D2Q4 grids the 32-bit offsets allow (2^27 - 128 cells in
+    FP64, 2^28 - 256 with FP32 storage: four planes of the cells rounded up to
+    64 plus 1 KB fit in 4 GiB) pass the configuration check, and one cell more
+    fails it (host-side check, no device call)."""
+    from paper_2609_10639_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        pytest.skip("libvlbm.so not built")
+    cap = (1 << 27) - 128 if precision == 0 else (1 << 28) - 256
+    assert nx * ny == cap + (0 if ok else 1)
+    c = _config(2, nx, ny, precision)
+    assert _native.lib().vlbm_check_config(ctypes.byref(c)) == (_native.OK if ok else _native.EINVAL)

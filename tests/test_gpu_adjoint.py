@@ -8,8 +8,9 @@ Tolerances: FP64 adjoint vs reference gradient, relative L2 <= 1e-9 (only
 rounding order differs); FP64 adjoint vs central differences at full size,
 1e-4 per direction; FP32 forms, relative L2 <= 1e-3 against the reference on
 small grids and against the FP64 adjoint at full size (Sensor A; 3e-3 for pure
-FP32 arithmetic over 625 steps).  With Sensor B the FP32 forms miss 1e-3 at full
-size (expected failure, reason in the test).
+FP32 arithmetic over 625 steps).  With Sensor B at full size (the adjoint
+workload) FP32 storage with FP64 arithmetic meets 1e-3; FP32 arithmetic misses
+it (expected failure with the measured value, beside a passing bound).
 
 Inputs with piecewise-constant states (Sod, Riemann, BZT) carry a seeded
 perturbation: exact ties of the max-normalisers M_k between plateau cells make
@@ -181,30 +182,54 @@ def test_full_size_fp32_adjoint_sensor_a(precision, tol):
     assert _rel(g, g64) <= tol
 
 
-@pytest.mark.xfail(strict=False, reason="FP32 storage noise reaches the Ducros ratio where dilatation and vorticity "
-                                        "are both near zero (eps_theta = 1e-12); the FP32 gradient of the Sensor B "
-                                        "workload sits 3e-2 to 5e-2 from the FP64 one")
-@pytest.mark.parametrize("precision", ["fp32_mixed", "fp32"])
+_C5_GRADIENTS = {}
+
+
+def _c5_gradient(precision):
+    if precision not in _C5_GRADIENTS:
+        W0, cfg, rho_t, steps = _c5(2)
+        _C5_GRADIENTS[precision] = _gpu_gradient(cfg, W0, rho_t, steps, precision)[1]
+    return _C5_GRADIENTS[precision]
+
+
+@pytest.mark.parametrize("precision", [
+    "fp32_mixed",
+    pytest.param("fp32", marks=pytest.mark.xfail(
+        strict=False, reason="FP32 arithmetic over 625 forward and 625 adjoint steps: relative L2 1.6e-3 from the "
+                             "FP64 gradient; FP32 storage with FP64 arithmetic meets 1e-3 (6.0e-4)"))])
 def test_full_size_fp32_adjoint_sensor_b(precision):
-    W0, cfg, rho_t, steps = _c5(2)
-    g64 = _gpu_gradient(cfg, W0, rho_t, steps, "fp64")[1]
-    g = _gpu_gradient(cfg, W0, rho_t, steps, precision)[1]
+    """The adjoint workload as configured (Sensor B): the FP32 gradient against
+    the FP64 adjoint (itself pinned to finite differences above)."""
+    g64, g = _c5_gradient("fp64"), _c5_gradient(precision)
     _say(precision, "Sensor B: rel L2 vs fp64 %.2e" % _rel(g, g64))
-    assert _rel(g, g64) <= 0.1      # measured bound, regression guard
-    assert _rel(g, g64) <= 1e-3     # the FP32 target
+    assert _rel(g, g64) <= 1e-3
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-3)])
+@pytest.mark.parametrize("precision,bound", [("fp32_mixed", 2e-3), ("fp32", 5e-3)])
+def test_full_size_fp32_adjoint_sensor_b_bound(precision, bound):
+    """Regression bound on the measured gaps (6.0e-4 and 1.6e-3)."""
+    g64, g = _c5_gradient("fp64"), _c5_gradient(precision)
+    assert _rel(g, g64) <= bound
+    if precision == "fp32":
+        _C5_GRADIENTS.clear()
+
+
+FP32_STEP_BOUND = {0: 1e-6, 1: 1e-5, 2: 3e-4}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape,bc,sensor", [((131, 97), (1, 1, 1, 1), 2), ((131, 97), (0, 0, 1, 1), 2),
                                              ((96, 160), (1, 1, 0, 0), 1), ((70, 70), (0, 0, 0, 0), 0)])
-def test_fused_and_multipass_adjoint_step(precision, tol, shape, bc, sensor, monkeypatch):
+def test_fused_and_multipass_adjoint_step(precision, shape, bc, sensor, monkeypatch):
     """One adjoint step on ragged grids spanning several strips and segments,
     with every boundary mix: the single-march form and the multi-pass form
     against the PyTorch FP64 vector-Jacobian product of the same step at the
-    same state (the GPU state, copied out).  FP32: rounding (6e-8) amplified by
-    the transposed sensor at the quadrant discontinuities, by how much depends
-    on the cotangent drawn (measured 7e-5 to 3.7e-4 over draws); held to the
-    1e-3 bound of the FP32 adjoint checks."""
+    same state (the GPU state, copied out).  Relative Linf bounds: FP64 1e-11;
+    FP32 per sensor, from rounding (6e-8) amplified by what the step's adjoint
+    does with it: constant beta 1e-6 (measured 1.5e-7), Sensor A 1e-5 (2.9e-6),
+    Sensor B 3e-4 (2.5e-5 to 4.1e-5: the transposed sensor at the quadrant
+    discontinuities)."""
+    tol = 1e-11 if precision == "fp64" else FP32_STEP_BOUND[sensor]
     from oracle.torch_ref import step_vjp
     from paper_2609_10639_amd import Solver
     nx, ny = shape

@@ -24,12 +24,32 @@ def test_copy_probe_copies_exactly(nbytes):
     assert int(dst[nbytes:].sum()) == 0
 
 
+@pytest.mark.parametrize("nbytes", [16, 4096 * 16 + 48, 1 << 26])
+def test_read_probe_reads_every_word(nbytes):
+    """Read-only mode: the XOR of the per-workgroup words equals the XOR of
+    every 16-byte word of the source."""
+    g = torch.Generator(device="cpu").manual_seed(nbytes % 997)
+    host = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, generator=g)
+    src = host.cuda()
+    out_bytes = _native.lib().vlbm_copy_probe_read_bytes(nbytes)
+    assert 16 <= out_bytes <= 128 * 1024
+    dst = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
+    _native.copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, torch.cuda.current_stream().cuda_stream, 1)
+    torch.cuda.synchronize()
+    words = host.numpy().view(np.uint64).reshape(-1, 2)
+    expect = np.bitwise_xor.reduce(words, axis=0)
+    got = np.bitwise_xor.reduce(dst.cpu().numpy().view(np.uint64).reshape(-1, 2), axis=0)
+    assert np.array_equal(got, expect)
+
+
 def test_copy_probe_rejects_bad_arguments():
     L = _native.lib()
     buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
     p = ctypes.c_void_p(buf.data_ptr())
-    assert L.vlbm_copy_probe(p, p, 17, None) == _native.EINVAL
-    assert L.vlbm_copy_probe(None, p, 16, None) == _native.EINVAL
-    assert L.vlbm_copy_probe(p, None, 16, None) == _native.EINVAL
-    assert L.vlbm_copy_probe(p, p, 0, None) == _native.OK   # nothing to copy
+    assert L.vlbm_copy_probe(p, p, 17, None, 0) == _native.EINVAL
+    assert L.vlbm_copy_probe(None, p, 16, None, 0) == _native.EINVAL
+    assert L.vlbm_copy_probe(p, None, 16, None, 0) == _native.EINVAL
+    assert L.vlbm_copy_probe(p, p, 16, None, 2) == _native.EINVAL
+    assert L.vlbm_copy_probe(p, p, 0, None, 0) == _native.OK   # nothing to copy
+    assert L.vlbm_copy_probe(p, p, 0, None, 1) == _native.OK
     torch.cuda.synchronize()
