@@ -1,10 +1,10 @@
 """Benchmark of the VLBM hot path on one MI355X.
 
-Headline workload: the four-quadrant Riemann problem, configuration 12 of
-Sec. IV.E, on [0,1]^2 at 4096^2 cells, outflow edges, ideal gas gamma = 1.4,
-D2Q4 with Sensor B (beta_min 0.7, beta_max 1, C 16), CFL 0.45 with the link
-speed retargeted every step, FP32 populations and FP32 arithmetic (clock,
-reductions and totals in FP64).  A step is one fused D2Q4 lattice update of the
+Headline workload: the four-quadrant Riemann problem, configuration 3 of
+Sec. IV.E (interacting shocks), on [0,1]^2 at 4096^2 cells, outflow edges,
+ideal gas gamma = 1.4, D2Q4 with Sensor B (beta_min 0.7, beta_max 1, C 16),
+CFL 0.45 with the link speed retargeted every 4 steps, FP32 populations and
+FP32 arithmetic (clock, reductions and totals in FP64).  A step is one fused D2Q4 lattice update of the
 whole grid (moments, EOS closure, retarget + reprojection, sensor, collision,
 streaming and the reductions for the next step), launched through the C ABI;
 `value` is lattice updates per second (MLUPS) over the K timed steps, the
@@ -16,12 +16,10 @@ Beside it on the same JSON line:
                 with HIP events on the library's stream; `traffic` = measured
                 HBM bytes per launch from the committed hardware-counter summary
                 when it was taken on the current kernel source (else null);
-  c3            the Riemann configurations at 4096^2: configuration 12 (Sensor B)
-                in FP64 and FP32 storage with FP64 arithmetic, configuration 3
-                (interacting shocks, Sensor A: under Sensor B it loses
-                admissibility from 800^2 up) in all three forms, and whole runs
-                to t = 0.25 timed by the host clock (batches and their host
-                read-backs included);
+  c3            the Riemann configurations at 4096^2: configuration 3 in FP64
+                and FP32 storage with FP64 arithmetic, configuration 12 in all
+                three forms, and whole runs to t = 0.25 timed by the host clock
+                (batches and their host read-backs included);
   c1_sod        the Sod tube, 1000 cells, whole run to t = 0.2 (launch-bound);
   c2_vortex     the isentropic vortex at 1024^2 (all forms) and 4096^2;
   c4_bzt        the dense-gas tube, 8192 cells, whole runs (launch-bound), and
@@ -48,11 +46,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "d2q4_fp32_riemann12_4096_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "d2q4_fp32_riemann3_4096_traffic.txt")
 KERNEL_SOURCES = ("paper_2609_10639_amd/csrc/vlbm_step2d.hip", "paper_2609_10639_amd/csrc/vlbm_planes.hpp",
                   "paper_2609_10639_amd/csrc/vlbm_common.hpp", "paper_2609_10639_amd/csrc/vlbm_api.cpp")
-WORKLOAD = ("four-quadrant Riemann problem, configuration 12, [0,1]^2, outflow, ideal gas gamma 1.4, D2Q4, "
-            "Sensor B (0.7, 1, 16), CFL 0.45 retargeted every step, FP32 populations and arithmetic")
+WORKLOAD = ("four-quadrant Riemann problem, configuration 3 (interacting shocks), [0,1]^2, outflow, ideal gas "
+            "gamma 1.4, D2Q4, Sensor B (0.7, 1, 16), CFL 0.45 retargeted every 4 steps, FP32 populations and arithmetic")
 
 
 def parse():
@@ -74,19 +72,18 @@ def parse():
 # ------------------------------------------------------------------ workloads
 
 def riemann_cfg(n, config):
-    """Configuration 12 with Sensor B, or configuration 3 with Sensor A (the
-    Ducros gate of Sensor B loses admissibility on it from 800^2 up)."""
+    """Configuration 3 or 12 under Sensor B, link speed retargeted every 4 steps."""
     from paper_2609_10639_amd import problems as pr
     W0, dx = pr.riemann2d(n, config)
-    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2 if config == 12 else 1,
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, retarget_every=pr.RETARGET_2D, sensor=2,
                     **pr.SENSOR_2D, **pr.IDEAL_AIR.config())
 
 
 def vortex_cfg(n):
     from paper_2609_10639_amd import problems as pr
     W0, dx = pr.vortex(n)
-    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D,
-                    **pr.IDEAL_AIR.config())
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, retarget_every=pr.RETARGET_2D, sensor=2,
+                    **pr.SENSOR_2D, **pr.IDEAL_AIR.config())
 
 
 def sod_cfg(n):
@@ -110,7 +107,8 @@ def bzt_cfg(n, dim):
         cfg = dict(dim=1, nx=n, ny=1, dx=dx, bc=(1, 1, 1, 1), cfl=0.5, sensor=1, **pr.SENSOR_1D)
     else:
         W0, dx = pr.bzt_extrusion(n)
-        cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D)
+        cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 0, 0), cfl=0.45, retarget_every=pr.RETARGET_2D, sensor=2,
+                   **pr.SENSOR_2D)
     return W0, dict(cfg, **pr.VDW_REDUCED_CV50.config())
 
 
@@ -156,7 +154,7 @@ def time_steps(W0, cfg, precision, steps, warmup):
 
 
 def whole_run(W0, cfg, precision, t_end):
-    """One run from W0 to t_end (every step retargeted, landing exactly), timed
+    """One run from W0 to t_end (retargeted as configured, landing exactly), timed
     by the host clock around run_to_time: the whole-job rate, batches and their
     host read-backs included."""
     import torch
@@ -304,7 +302,7 @@ sys.path.insert(0, %r)
 from bench import riemann_cfg
 from oracle import core
 n, steps = %d, %d
-W0, cfg = riemann_cfg(n, 12)
+W0, cfg = riemann_cfg(n, 3)
 o = core.Oracle(**cfg)
 o.init(W0)
 o.step()
@@ -383,7 +381,7 @@ def only(a):
     if o.startswith("adjoint"):
         return dict(only=o, **adjoint_ratio("fp32" if o.endswith("32") else "fp64"))
     if o == "headline":
-        W0, cfg, prec = *riemann_cfg(n, 12), "fp32"
+        W0, cfg, prec = *riemann_cfg(n, 3), "fp32"
     else:
         name, prec = o.rsplit("_", 1)
         prec = {"fp64": "fp64", "fp32": "fp32", "mixed": "fp32_mixed"}[prec]
@@ -407,7 +405,7 @@ def main():
 
     n = a.grid
     cells = n * n
-    W0, cfg = riemann_cfg(n, 12)
+    W0, cfg = riemann_cfg(n, 3)
     ms = time_steps(W0, cfg, "fp32", a.steps, a.warmup)
     out = {
         "metric": "MLUPS and % of HBM roofline (FP64 vs FP32), adjoint/forward step-cost ratio",
@@ -427,14 +425,14 @@ def main():
     }
     if not a.no_extra:
         k = max(20, a.steps // 4)
-        c3 = {"config12_sensorB": per_step(W0, cfg, ("fp64", "fp32_mixed"), k, 5)}
-        c3["config12_sensorB"]["fp32_to_t_end"] = whole_run(W0, cfg, "fp32", 0.25)
-        c3["config12_sensorB"]["fp64_to_t_end"] = whole_run(W0, cfg, "fp64", 0.25)
+        c3 = {"config3": per_step(W0, cfg, ("fp64", "fp32_mixed"), k, 5)}
+        c3["config3"]["fp32_to_t_end"] = whole_run(W0, cfg, "fp32", 0.25)
+        c3["config3"]["fp64_to_t_end"] = whole_run(W0, cfg, "fp64", 0.25)
         del W0
-        W3, cf3 = riemann_cfg(n, 3)
-        c3["config3_sensorA"] = per_step(W3, cf3, ("fp32", "fp64", "fp32_mixed"), k, 5)
-        c3["config3_sensorA"]["fp32_to_t_end"] = whole_run(W3, cf3, "fp32", 0.25)
-        del W3
+        W12, cf12 = riemann_cfg(n, 12)
+        c3["config12"] = per_step(W12, cf12, ("fp32", "fp64", "fp32_mixed"), k, 5)
+        c3["config12"]["fp32_to_t_end"] = whole_run(W12, cf12, "fp32", 0.25)
+        del W12
         out["c3"] = c3
         Ws, cs = sod_cfg(1000)
         out["c1_sod"] = {"launch_bound": True, "fp64_to_t_end": whole_run(Ws, cs, "fp64", 0.2)}

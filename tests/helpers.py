@@ -21,27 +21,28 @@ def bzt1d_case(n=1024):
 
 def vortex_case(n=128):
     W0, dx = pr.vortex(n)
-    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D, **IDEAL), 10.0
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, retarget_every=pr.RETARGET_2D, sensor=2,
+                    **pr.SENSOR_2D, **IDEAL), 10.0
 
 
 def riemann_case(n=128, config=3, sensor=2):
-    """Four-quadrant problem to t = 0.25 with Sensor B, or with Sensor A (no
-    Ducros gate) for configuration 3 on fine grids, where the gate loses
-    admissibility (from 800^2 up)."""
+    """Four-quadrant problem to t = 0.25, outflow, Sensor B (or the sensor given)."""
     W0, dx = pr.riemann2d(n, config)
-    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=sensor, **pr.SENSOR_2D, **IDEAL), 0.25
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, retarget_every=pr.RETARGET_2D, sensor=sensor,
+                    **pr.SENSOR_2D, **IDEAL), 0.25
 
 
 def riemann_bzt_case(n=128):
     """BZT four-quadrant problem (Sec. IV.F, Eq. 49) to t = 0.35, outflow, Sensor B."""
     W0, dx = pr.riemann2d(n, "bzt")
-    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, sensor=2, **pr.SENSOR_2D,
-                    **pr.BZT_GAS.config()), pr.RIEMANN_T_END["bzt"]
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 1, 1), cfl=0.45, retarget_every=pr.RETARGET_2D, sensor=2,
+                    **pr.SENSOR_2D, **pr.BZT_GAS.config()), pr.RIEMANN_T_END["bzt"]
 
 
 def bzt2d_case(n=256):
     W0, dx = pr.bzt_extrusion(n)
-    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 0, 0), cfl=0.45, sensor=2, **pr.SENSOR_2D, **VDW), 0.2
+    return W0, dict(dim=2, nx=n, ny=n, dx=dx, bc=(1, 1, 0, 0), cfl=0.45, retarget_every=pr.RETARGET_2D, sensor=2,
+                    **pr.SENSOR_2D, **VDW), 0.2
 
 
 def energy_gauge(W0):
@@ -58,7 +59,8 @@ def gresho_case(n=100, sensor="B"):
     stable constant beta 0.995 (the paper's rule for beta_min), or that
     constant beta alone."""
     W0, dx = pr.gresho(n)
-    cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, **pr.IDEAL_MONO.config())
+    cfg = dict(dim=2, nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, retarget_every=pr.RETARGET_2D,
+               **pr.IDEAL_MONO.config())
     if sensor == "B":
         cfg.update(sensor=2, beta_min=0.995, beta_max=1.0, c_sensor=16.0)
     else:

@@ -59,8 +59,8 @@ def _stream_case(nx, ny, bc, speed):
     Lx = nx * dx
     centre = (0.3 * Lx, 0.5 * ny * dx) if speed > 0 else (0.7 * Lx, 0.5 * ny * dx)
     W0, Winf = pr.vortex_in_stream(nx, ny, dx, speed=speed, centre=centre)
-    cfg = dict(dim=2, nx=nx, ny=ny, dx=dx, bc=bc, bc_state=(tuple(Winf), tuple(Winf)), cfl=0.45, sensor=2,
-               **pr.SENSOR_2D, **pr.IDEAL_AIR.config())
+    cfg = dict(dim=2, nx=nx, ny=ny, dx=dx, bc=bc, bc_state=(tuple(Winf), tuple(Winf)), cfl=0.45,
+               retarget_every=pr.RETARGET_2D, sensor=2, **pr.SENSOR_2D, **pr.IDEAL_AIR.config())
     return W0, cfg
 
 

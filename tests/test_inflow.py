@@ -57,7 +57,8 @@ def test_uniform_stream_stays_uniform_2d(bc):
     W0 = pr.conserved(pr.IDEAL_AIR, np.full((n, n + 5), rho), np.full((n, n + 5), u), np.full((n, n + 5), P),
                       np.full((n, n + 5), v))
     Wb = tuple(W0[:, 0, 0])
-    o = oracle_for(dict(dim=2, nx=n + 5, ny=n, dx=1.0 / n, bc=bc, bc_state=(Wb, Wb), cfl=0.45, sensor=2,
+    o = oracle_for(dict(dim=2, nx=n + 5, ny=n, dx=1.0 / n, bc=bc, bc_state=(Wb, Wb), cfl=0.45,
+                        retarget_every=pr.RETARGET_2D, sensor=2,
                         **pr.SENSOR_2D, **IDEAL), W0)
     for _ in range(30):
         o.step()
@@ -69,7 +70,8 @@ def test_pinned_equals_outflow_while_the_edge_is_quiet():
     inflow edge to the free stream gives the outflow result bit for bit until
     non-equilibrium content reaches the edge cell (a few steps here)."""
     W0, Winf = pr.vortex_in_stream(80, 40, 0.25, speed=2.0, centre=(12.0, 5.0))
-    base = dict(dim=2, nx=80, ny=40, dx=0.25, cfl=0.45, sensor=2, **pr.SENSOR_2D, **IDEAL)
+    base = dict(dim=2, nx=80, ny=40, dx=0.25, cfl=0.45, retarget_every=pr.RETARGET_2D, sensor=2, **pr.SENSOR_2D,
+                **IDEAL)
     a = oracle_for(dict(base, bc=(1, 1, 0, 0)), W0)
     b = oracle_for(dict(base, bc=(2, 1, 0, 0), bc_state=(tuple(Winf), None)), W0)
     for _ in range(3):

@@ -101,12 +101,13 @@ def test_bzt_vortex_is_in_radial_balance_and_has_a_classical_core():
 
 def shock_vortex_config(case, nx, strength=2.0):
     """D2Q4 run of Sec. IV.H: inflow edge pinned to the upstream state,
-    outflow on the right, periodic in y; Sensor B (0.7, 1, 16), CFL 0.45."""
+    outflow on the right, periodic in y; Sensor B (0.7, 1, 16), CFL 0.45,
+    retargeted every 4 steps."""
     ny = nx * 3 // 8
     W0, dx, W_in = pr.shock_vortex(case, nx, ny, strength=strength)
     gas = pr.SHOCK_VORTEX[case]["gas"]
-    cfg = dict(dim=2, nx=nx, ny=ny, dx=dx, bc=(2, 1, 0, 0), bc_state=(tuple(W_in), None), cfl=0.45, sensor=2,
-               **pr.SENSOR_2D, **gas.config())
+    cfg = dict(dim=2, nx=nx, ny=ny, dx=dx, bc=(2, 1, 0, 0), bc_state=(tuple(W_in), None), cfl=0.45,
+               retarget_every=pr.RETARGET_2D, sensor=2, **pr.SENSOR_2D, **gas.config())
     return W0, cfg, pr.SHOCK_VORTEX[case]["t_end"]
 
 
