@@ -203,6 +203,23 @@ vlbm_status vlbm_raw_step(vlbm_ctx* ctx, const void* f_in, const double* norms_i
 vlbm_status vlbm_raw_adjoint_step(vlbm_ctx* ctx, const void* f_n, const double* norms_n,
                                   const void* lam_np1, void* lam_n);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): vlbm_raw_adjoint_step
+ * with the per-wavefront records of the fused D2Q4 adjoint march (its only
+ * scratch) in a static device array of 4096 records (384 KiB) instead of the
+ * context's buffer.  It allocates nothing and calls no allocating routine; the
+ * first call on a device looks up that device's copy of the array.  Same
+ * arguments, result and stream ordering as vlbm_raw_adjoint_step, bit for bit.
+ * VLBM_EINVAL for a context on the multi-pass adjoint (D1Q2, or
+ * VLBM_ADJ_MULTIPASS set at creation) or a grid whose tiling needs more than
+ * 4096 march records (strips of 56 columns times row segments), with the
+ * counts in vlbm_last_error.  Every call on one GPU shares that GPU's array
+ * and overwrites all of the records it reads, so nothing carries over between
+ * calls; calls that overlap in time on one GPU (other streams, other threads)
+ * race on it. */
+vlbm_status vlbm_raw_adjoint_step_static(vlbm_ctx* ctx, const void* f_n, const double* norms_n,
+                                         const void* lam_np1, void* lam_n);
+
 /* Adjoint of vlbm_raw_init: W0bar (FP64 (dim+2, ny, nx), overwritten) =
  * (d f0/d W0)^T lam0 at the state W0. */
 vlbm_status vlbm_raw_init_adjoint(vlbm_ctx* ctx, const double* W0, const void* lam0, double* W0bar);

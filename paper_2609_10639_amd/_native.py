@@ -77,6 +77,7 @@ _SIGS = [
     ("vlbm_raw_init", ctypes.c_int, [_P, _P, _P, _P]),
     ("vlbm_raw_step", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("vlbm_raw_adjoint_step", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("vlbm_raw_adjoint_step_static", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("vlbm_raw_init_adjoint", ctypes.c_int, [_P, _P, _P, _P]),
     ("vlbm_raw_moments", ctypes.c_int, [_P, _P, _P]),
     ("vlbm_raw_moments_adjoint", ctypes.c_int, [_P, _P, _P]),

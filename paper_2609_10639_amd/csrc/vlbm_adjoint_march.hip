@@ -30,6 +30,8 @@
 // normaliser term at the maximisers.
 // Non-smooth points: d clip/dX = 1 on (0, 1), 0 elsewhere; d sqrt(s)/ds := 0 at
 // s = 0; the M_k sub-gradient goes to the first maximiser in (alpha, y, x) order.
+#include <mutex>
+
 #include "vlbm_adjoint_math.hpp"
 #include "vlbm_aux.hpp"
 #include "vlbm_planes.hpp"
@@ -626,6 +628,40 @@ hipError_t launch_adjoint_march(const KParams& p, int prec, const void* f_n, con
     case PREC_FP32_MIXED: return march_t<float, double>(p, f_n, norms_n, lam_np1, lam_n, rec, st);
     }
     return hipErrorInvalidValue;
+}
+
+// Scratch of the allocation-free adjoint step: the per-wavefront records of the
+// march (kRecDoubles each) in a file-scope device array, which every GPU the
+// library runs on holds until the process ends.  Host code never passes the
+// array's name to a kernel: it passes the device address that
+// hipGetSymbolAddress returns for the GPU at hand, looked up once per device.
+static __device__ __align__(256) double scratch[kStaticMarchRecords * kRecDoubles];
+
+constexpr int kMaxDevices = 64;
+
+hipError_t adjm_static_scratch(int device, double** out)
+{
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<double*>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace vlbm

@@ -52,6 +52,7 @@ struct vlbm_ctx {
     AdjScratch adj{};
     bool adj_march = false;        // fused single-march adjoint (D2Q4)
     hipStream_t stream;
+    int device = 0;                // current device at creation: where the buffers live
     long long n = 0;
     double t = 0.0, c = 0.0;
     bool initialised = false;
@@ -268,6 +269,10 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
     }
     vlbm_ctx* ctx = new vlbm_ctx();
     ctx->cfg = *cfg;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return VLBM_EDEVICE;
+    }
     ctx->stream = (hipStream_t)cfg->stream;
     ctx->D = cfg->dim;
     ctx->Q = 2 * cfg->dim;
@@ -694,6 +699,30 @@ vlbm_status vlbm_raw_adjoint_step(vlbm_ctx* ctx, const void* f_n, const double* 
         HIPCHK(ctx, launch_adjoint_march(ctx->kp, ctx->prec, f_n, norms_n, lam_np1, lam_n, ctx->adj.rec, ctx->stream));
     else
         HIPCHK(ctx, launch_adjoint_step(ctx->kp, ctx->prec, f_n, norms_n, lam_np1, lam_n, ctx->adj, ctx->stream));
+    return VLBM_OK;
+}
+
+vlbm_status vlbm_raw_adjoint_step_static(vlbm_ctx* ctx, const void* f_n, const double* norms_n, const void* lam_np1,
+                                         void* lam_n)
+{
+    if (vlbm_status st = need_frozen(ctx)) return st;
+    if (vlbm_status st = need_adjoint_support(ctx)) return st;
+    if (!f_n || !norms_n || !lam_np1 || !lam_n) return fail(ctx, VLBM_EINVAL, "null argument");
+    if (lam_np1 == lam_n) return fail(ctx, VLBM_EINVAL, "lam_np1 and lam_n must differ");
+    if (!ctx->adj_march)
+        return fail(ctx, VLBM_EINVAL, "the allocation-free adjoint step covers the fused D2Q4 march only");
+    const int need = adjoint_march_records(ctx->kp);
+    if (need > kStaticMarchRecords) {
+        char buf[200];
+        snprintf(buf, sizeof buf,
+                 "the grid's tiling needs %d march records, the static scratch of the allocation-free adjoint step "
+                 "holds %d",
+                 need, kStaticMarchRecords);
+        return fail(ctx, VLBM_EINVAL, buf);
+    }
+    double* rec = nullptr;
+    HIPCHK(ctx, adjm_static_scratch(ctx->device, &rec));
+    HIPCHK(ctx, launch_adjoint_march(ctx->kp, ctx->prec, f_n, norms_n, lam_np1, lam_n, rec, ctx->stream));
     return VLBM_OK;
 }
 

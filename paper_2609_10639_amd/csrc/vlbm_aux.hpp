@@ -49,6 +49,11 @@ int adjoint_march_records(const KParams& p);
 bool adjoint_march_supported(const KParams& p);
 hipError_t launch_adjoint_march(const KParams& p, int prec, const void* f_n, const double* norms_n,
                                 const void* lam_np1, void* lam_n, double* rec, hipStream_t st);
+// records of the march that the allocation-free adjoint step's static scratch
+// holds (12 doubles each: 384 KiB), and that scratch's device address on
+// `device` (looked up on the first call for that device)
+constexpr int kStaticMarchRecords = 4096;
+hipError_t adjm_static_scratch(int device, double** out);
 hipError_t launch_init_adjoint(const KParams& p, int prec, const double* W0, long long ncell, const void* lam0,
                                double* W0bar, hipStream_t st);
 

@@ -194,6 +194,11 @@ class Solver:
         self._chk(N.lib().vlbm_raw_adjoint_step(self._h, self._pop(f_n), self._nrm(norms_n), self._pop(lam_np1),
                                                 self._pop(lam_n)))
 
+    def raw_adjoint_step_static(self, f_n, norms_n, lam_np1, lam_n):
+        """raw_adjoint_step with the library's static scratch: allocates nothing."""
+        self._chk(N.lib().vlbm_raw_adjoint_step_static(self._h, self._pop(f_n), self._nrm(norms_n),
+                                                       self._pop(lam_np1), self._pop(lam_n)))
+
     def raw_init_adjoint(self, W0, lam0, W0bar):
         self._chk(N.lib().vlbm_raw_init_adjoint(self._h, self._fld(W0), self._pop(lam0), self._fld(W0bar)))
 
