@@ -30,7 +30,9 @@ Beside it on the same JSON line:
                 (1024^2 perturbed vortex, frozen dt = 1/625, Sensor B), per
                 step and end to end (checkpointed forward + backward);
   copy          plain device copies of one 4096^2 FP64 population array and a
-                read-only stream: the attainable bandwidth;
+                read-only stream: the attainable bandwidth; and the step's own
+                access pattern without its arithmetic (march probe, FP32 and
+                FP64 at the headline grid): the ceiling of that pattern;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the headline
                 workload, on all host threads and on one.
 """
@@ -340,6 +342,24 @@ def cpu_baseline(n, steps_all, steps_one):
             "build": "gcc -O3 -ffp-contract=off -fopenmp, FP64"}
 
 
+def march_probe(W0, cfg, precision, steps, warmup):
+    """The step's loads and stores without its arithmetic (vlbm_probe_march),
+    timed like the step; returns the line of the step's algorithmic bytes."""
+    import torch
+    from paper_2609_10639_amd import Solver
+    s = Solver(precision=precision, **cfg)
+    s.init(W0)
+    s.probe_march(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record(s.stream)
+    s.probe_march(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    s.close()
+    return line(e0.elapsed_time(e1) / steps, cfg["nx"] * cfg["ny"], 2, precision)
+
+
 def copy_bw(nbytes, steps, warmup):
     """Plain device copies of `nbytes` (torch's copy_, the library's copy probe)
     and the probe's read-only stream: attainable bandwidth, and the reference
@@ -378,6 +398,9 @@ def only(a):
     n = a.grid
     if o == "copy":
         return dict(only=o, **copy_bw(16 * n * n * 8, a.steps, a.warmup))
+    if o.startswith("march"):
+        W0, cfg = riemann_cfg(n, 3)
+        return dict(only=o, **march_probe(W0, cfg, "fp32" if o.endswith("32") else "fp64", a.steps, a.warmup))
     if o.startswith("adjoint"):
         return dict(only=o, **adjoint_ratio("fp32" if o.endswith("32") else "fp64"))
     if o == "headline":
@@ -453,6 +476,8 @@ def main():
         del W1
         out["adjoint"] = [adjoint_ratio("fp32"), adjoint_ratio("fp64")]
         out["copy"] = copy_bw(16 * n * n * 8, 20, 3)
+        Wm, cm = riemann_cfg(n, 3)
+        out["copy"]["march_probe"] = {p: march_probe(Wm, cm, p, k, 5) for p in ("fp32", "fp64")}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, a.cpu_steps, a.cpu_steps_1t)
     print(json.dumps(out), flush=True)

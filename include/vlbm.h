@@ -248,6 +248,16 @@ const char* vlbm_last_error(const vlbm_ctx* ctx);
 vlbm_status vlbm_copy_probe(const void* src, void* dst, size_t bytes, void* stream, int32_t mode);
 size_t vlbm_copy_probe_read_bytes(size_t bytes);
 
+/* Measurement aid, not part of the method: `nlaunch` launches of a kernel with
+ * the D2Q4 step's memory access pattern and none of its arithmetic (same grid,
+ * tiling, halos, addressing and loads in flight; loads every population plane
+ * of each row, stores the owned cells' values where the step stores its
+ * post-collision populations), reading the current populations and writing the
+ * context's spare population buffer, so the state is left as it was.  Its rate
+ * bounds what the step's access pattern can move through HBM.  Stream-ordered,
+ * no synchronisation.  VLBM_EINVAL for a D1Q2 or uninitialised context. */
+vlbm_status vlbm_probe_march(vlbm_ctx* ctx, int32_t nlaunch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -84,6 +84,7 @@ _SIGS = [
     ("vlbm_last_error", ctypes.c_char_p, [_P]),
     ("vlbm_copy_probe", ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, ctypes.c_int32]),
     ("vlbm_copy_probe_read_bytes", ctypes.c_size_t, [ctypes.c_size_t]),
+    ("vlbm_probe_march", ctypes.c_int, [_P, ctypes.c_int32]),
 ]
 EXPORTED = [name for name, _, _ in _SIGS]
 

@@ -760,4 +760,15 @@ vlbm_status vlbm_copy_probe(const void* src, void* dst, size_t bytes, void* stre
 
 size_t vlbm_copy_probe_read_bytes(size_t bytes) { return read_probe_out_bytes(bytes); }
 
+vlbm_status vlbm_probe_march(vlbm_ctx* ctx, int32_t nlaunch)
+{
+    if (!ctx || nlaunch < 0) return fail(ctx, VLBM_EINVAL, "bad argument");
+    if (ctx->D != 2) return fail(ctx, VLBM_EINVAL, "the march probe is the D2Q4 step's access pattern");
+    if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
+    const void* fin = ctx->f[ctx->n & 1];
+    void* spare = ctx->f[(ctx->n + 1) & 1];   // free between steps
+    for (int i = 0; i < nlaunch; ++i) HIPCHK(ctx, launch_march_probe(ctx->kp, ctx->fp32, fin, spare, ctx->stream));
+    return VLBM_OK;
+}
+
 }  // extern "C"

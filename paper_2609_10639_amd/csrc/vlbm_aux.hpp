@@ -8,6 +8,8 @@ namespace vlbm {
 hipError_t launch_step_d2q4(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st);
 hipError_t launch_step_d1q2(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st);
 int step_d2q4_blocks_per_cu(const KParams& p, int prec);
+// measurement aid: the D2Q4 step's loads and stores without its arithmetic
+hipError_t launch_march_probe(const KParams& p, bool fp32, const void* fin, void* fout, hipStream_t st);
 
 hipError_t launch_reset_ctl(double* ring, unsigned long long* stop_at, int* err, hipStream_t st);
 hipError_t launch_reset_stop(unsigned long long* stop_at, int* err, hipStream_t st);

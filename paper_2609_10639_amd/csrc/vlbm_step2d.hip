@@ -496,6 +496,87 @@ hipError_t launch_step_d2q4(const KParams& p, const KStep& s, int prec, const vo
     return hipErrorInvalidValue;
 }
 
+// Measurement aid: the step's memory access pattern with none of its
+// arithmetic.  Same grid, tiling (strips with their halo lanes, segments with
+// their 3-row halos, wpg wavefronts marching in step, XCD remapping), buffer
+// addressing and two rows of loads in flight; every row's 16 planes are loaded
+// and the owned cells' values are stored where the step stores post-collision
+// populations: the x planes into the same row (moved one lane across the
+// wavefront, as streaming moves them), the +y planes into the row above, the -y
+// planes into the row below.  It bounds what the step's own access pattern can
+// move through HBM.
+template <typename S>
+__global__ void __launch_bounds__(256) k_march_probe(const KParams P, const S* __restrict__ fin, S* __restrict__ fout)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const Planes in = make_planes(fin, (unsigned)P.plane), out = make_planes((const S*)fout, (unsigned)P.plane);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int group = tile % P.ngroups, seg = tile / P.ngroups;
+    const int strip = group * P.wpg + wave;
+    const int halo = (64 - P.strip_w) / 2;
+    const int X = strip * P.strip_w - halo + lane;
+    int cx = X;
+    if (X < 0) cx = P.bc[0] == 0 ? wrap_index(X, P.nx) : 0;
+    else if (X >= P.nx) cx = P.bc[1] == 0 ? wrap_index(X, P.nx) : P.nx - 1;
+    const bool owner = lane >= halo && lane < halo + P.strip_w && X < P.nx && strip < P.nstrips;
+    const bool clo = P.bc[2] == 1, chi = P.bc[3] == 1;
+    const int y0 = seg * P.seg_h, y1 = min(y0 + P.seg_h, P.ny);
+    const int Rb = clo ? max(y0 - 3, 0) : y0 - 3, Re = chi ? min(y1 + 2, P.ny - 1) : y1 + 2;
+    const unsigned rowb = (unsigned)P.nx * (unsigned)sizeof(S), col = (unsigned)X * (unsigned)sizeof(S);
+    S buf[3][16];
+    auto load_row = [&](int R, S* dst) {
+        const int mrow = (R < 0 || R >= P.ny) ? wrap_index(R, P.ny) : R;
+        const unsigned off = (unsigned)mrow * rowb + (unsigned)cx * (unsigned)sizeof(S);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dst[j] = bload(in, j, off, S());
+    };
+    auto row = [&](int R, S* cur) {
+        if (P.wpg > 1) __syncthreads();
+        S gx[8];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            gx[k] = dpp_move<kDppWaveShr1>(cur[k]);
+            gx[4 + k] = dpp_move<kDppWaveShl1>(cur[4 + k]);
+        }
+        if (!owner) return;
+        if (R >= y0 && R < y1)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bstore(out, j, (unsigned)R * rowb + col, gx[j]);
+        if (R + 1 >= y0 && R + 1 < y1)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bstore(out, 8 + k, (unsigned)(R + 1) * rowb + col, cur[8 + k]);
+        if (R - 1 >= y0 && R - 1 < y1)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bstore(out, 12 + k, (unsigned)(R - 1) * rowb + col, cur[12 + k]);
+    };
+    load_row(Rb, buf[0]);
+    load_row(min(Rb + 1, Re), buf[1]);
+    // unrolled by three so that the buffer index is a compile-time constant; the
+    // loads are unconditional (past the last row they re-read row Re, in bounds)
+    for (int R = Rb; R <= Re; R += 3) {
+        load_row(min(R + 2, Re), buf[2]);
+        row(R, buf[0]);
+        if (R + 1 <= Re) {
+            load_row(min(R + 3, Re), buf[0]);
+            row(R + 1, buf[1]);
+        }
+        if (R + 2 <= Re) {
+            load_row(min(R + 4, Re), buf[1]);
+            row(R + 2, buf[2]);
+        }
+    }
+}
+
+hipError_t launch_march_probe(const KParams& p, bool fp32, const void* fin, void* fout, hipStream_t st)
+{
+    const dim3 grid(p.ngroups * p.nsegs), block(64 * p.wpg);
+    if (fp32)
+        hipLaunchKernelGGL(k_march_probe<float>, grid, block, 0, st, p, (const float*)fin, (float*)fout);
+    else
+        hipLaunchKernelGGL(k_march_probe<double>, grid, block, 0, st, p, (const double*)fin, (double*)fout);
+    return hipGetLastError();
+}
+
 int step_d2q4_blocks_per_cu(const KParams& p, int prec)
 {
     int nb = 0;

@@ -169,6 +169,11 @@ class Solver:
         torch = _torch()
         return torch.zeros(N.NORMS_LEN, dtype=torch.float64, device="cuda")
 
+    def probe_march(self, nlaunch=1):
+        """Measurement aid: the step's access pattern without its arithmetic
+        (vlbm_probe_march), stream-ordered; the state is left as it was."""
+        self._chk(N.lib().vlbm_probe_march(self._h, int(nlaunch)))
+
     # The raw entry points read and write whole device arrays through plain
     # pointers: every tensor is checked for device, layout, dtype and size here,
     # so that a wrong one raises instead of being read past its end.

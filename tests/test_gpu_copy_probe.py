@@ -53,3 +53,27 @@ def test_copy_probe_rejects_bad_arguments():
     assert L.vlbm_copy_probe(p, p, 0, None, 0) == _native.OK   # nothing to copy
     assert L.vlbm_copy_probe(p, p, 0, None, 1) == _native.OK
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_march_probe_leaves_the_state(precision):
+    """The march probe reads the current populations and writes only the spare
+    buffer: the state, and the steps that follow, are those of a run without it."""
+    from helpers import riemann_case
+    from paper_2609_10639_amd import Solver
+    W0, cfg, _ = riemann_case(128, 3)
+    s = Solver(precision=precision, **cfg)
+    s.init(W0)
+    s.step(5)
+    f0, clock0 = s.f(), s.clock()
+    s.probe_march(3)
+    torch.cuda.synchronize()
+    assert np.array_equal(s.f(), f0) and s.clock() == clock0
+    s.step(2)
+    ref = Solver(precision=precision, **cfg)
+    ref.init(W0)
+    ref.step(7)
+    assert np.array_equal(s.f(), ref.f())
+    d1 = Solver(precision=precision, **dict(cfg, dim=1, ny=1, bc=(1, 1, 1, 1), sensor=1))
+    with pytest.raises(_native.VlbmError):
+        d1.probe_march(1)
