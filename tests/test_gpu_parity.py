@@ -603,3 +603,46 @@ def test_riemann512_whole_run_against_oracle(precision, config, sensor):
     _say(precision, "config", config, "512 whole run", n_g, n_o, ["%.2e/%.2e" % e for e in errs])
     for e in errs:
         assert e[1] <= (1e-9 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision,nx,ny,tol", [("fp32", 19200, 13981, 1e-5), ("fp64", 9600, 13981, 1e-11)])
+def test_largest_grid_against_oracle(precision, nx, ny, tol):
+    """The largest D2Q4 grid the 32-bit plane offsets allow (2^28 - 256 cells
+    with FP32 storage, 2^27 - 128 in FP64): a smooth field periodic with periods
+    64 in x and 41 in y on the periodic grid, two steps (Sensor B).  The global
+    maxima and every stencil are those of the 64 x 41 torus, so the oracle on
+    that torus computes the same update: every cell of the full grid must match
+    it, and the full grid must stay exactly periodic (an offset that wrapped
+    anywhere in the 4 GiB of a four-plane group would break both)."""
+    from paper_2609_10639_amd import problems as pr
+    px, py = 64, 41
+    assert nx % px == 0 and ny % py == 0
+    x = (np.arange(px) + 0.5) / px
+    y = (np.arange(py) + 0.5) / py
+    X, Y = np.meshgrid(x, y)
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+    P = 1.0 + 0.1 * np.cos(2 * np.pi * (X + Y))
+    block = pr.conserved(pr.IDEAL_AIR, rho, 0.3 * np.sin(2 * np.pi * Y), P, 0.2 * np.cos(2 * np.pi * X))
+    dx = 1.0 / px
+    cfg = dict(dim=2, nx=px, ny=py, dx=dx, bc=(0, 0, 0, 0), cfl=0.45, retarget_every=pr.RETARGET_2D, sensor=2,
+               **pr.SENSOR_2D, **pr.IDEAL_AIR.config())
+    o = oracle_for(cfg, block)
+    o.step()
+    o.step()
+    Wo = o.W()
+    _say("largest grid", precision, nx, ny, nx * ny)
+    W0 = np.tile(block, (1, ny // py, nx // px))
+    s = _solver(dict(cfg, nx=nx, ny=ny), precision)
+    s.init(W0)
+    del W0
+    s.step(2)
+    assert s.clock()[2] == 2 and abs(s.clock()[1] - o.clock()[1]) <= 1e-12 * o.clock()[1]
+    W = s.W().reshape(4, ny // py, py, nx // px, px)
+    s.close()
+    first = W[:, 0, :, 0, :].copy()
+    assert np.array_equal(W, np.broadcast_to(first[:, None, :, None, :], W.shape))   # exactly periodic
+    del W
+    errs = rel_errors(first, Wo)
+    _say(" errors against the oracle on the torus", ["%.2e/%.2e" % e for e in errs])
+    for e in errs:
+        assert e[0] <= tol
