@@ -20,9 +20,12 @@ Beside it on the same JSON line:
                 and FP32 storage with FP64 arithmetic, configuration 12 in all
                 three forms, and whole runs to t = 0.25 timed by the host clock
                 (batches and their host read-backs included);
-  c1_sod        the Sod tube, 1000 cells, whole run to t = 0.2 (launch-bound);
+  c1_sod        the Sod tube, 1000 cells, whole runs to t = 0.2 in one resident
+                workgroup (the library's path up to 4096 cells) and, for
+                comparison, with one launch per step;
   c2_vortex     the isentropic vortex at 1024^2 (all forms) and 4096^2;
-  c4_bzt        the dense-gas tube, 8192 cells, whole runs (launch-bound), and
+  c4_bzt        the dense-gas tube, 8192 cells, whole runs (one launch per
+                step: launch-bound), and
                 its 2-D extrusion at 2048^2 (all forms, shifted energy gauge in
                 FP32), per step and whole run to t = 0.2;
   d1q2          the D1Q2 step (Sod data) at 2^26 cells;
@@ -67,7 +70,7 @@ def parse():
     ap.add_argument("--cpu-steps-1t", type=int, default=2, help="oracle steps of the one-thread sample")
     ap.add_argument("--only", default="", help="profiling aid: one measurement, e.g. headline | r12_fp64 | "
                                                 "r3_fp32 | vortex1024_fp32 | bzt2048_fp32 | d1q2_fp32 | "
-                                                "adjoint32 | copy")
+                                                "adjoint32 | copy | c1")
     return ap.parse_args()
 
 
@@ -172,6 +175,27 @@ def whole_run(W0, cfg, precision, t_end):
     s.close()
     cells = cfg["nx"] * cfg["ny"]
     return {"t_end": t_end, "steps": n, "seconds": round(dt, 4), "MLUPS": round(n * cells / dt / 1e6, 1)}
+
+
+def small_1d_runs(W0, cfg, t_end, precisions):
+    """Whole runs of a D1Q2 grid small enough for the library's resident path
+    (batches of steps in one workgroup, populations on chip between steps: up
+    to 4096 cells), and the same runs with one launch per step (the path of
+    larger grids), each after one untimed run that loads the kernels."""
+    out = {"path": "resident: batches of steps in one workgroup"}
+    for p in precisions:
+        whole_run(W0, cfg, p, t_end)
+        out[p + "_to_t_end"] = whole_run(W0, cfg, p, t_end)
+    os.environ["VLBM_D1_RESIDENT"] = "0"
+    try:
+        per = {}
+        for p in precisions:
+            whole_run(W0, cfg, p, t_end)
+            per[p + "_to_t_end"] = whole_run(W0, cfg, p, t_end)
+        out["one_launch_per_step"] = per
+    finally:
+        del os.environ["VLBM_D1_RESIDENT"]
+    return out
 
 
 def bytes_per_lu(dim, precision):
@@ -401,6 +425,9 @@ def only(a):
     if o.startswith("march"):
         W0, cfg = riemann_cfg(n, 3)
         return dict(only=o, **march_probe(W0, cfg, "fp32" if o.endswith("32") else "fp64", a.steps, a.warmup))
+    if o == "c1":
+        W0, cfg = sod_cfg(1000)
+        return dict(only=o, **small_1d_runs(W0, cfg, 0.2, ("fp64", "fp32")))
     if o.startswith("adjoint"):
         return dict(only=o, **adjoint_ratio("fp32" if o.endswith("32") else "fp64"))
     if o == "headline":
@@ -458,7 +485,7 @@ def main():
         del W12
         out["c3"] = c3
         Ws, cs = sod_cfg(1000)
-        out["c1_sod"] = {"launch_bound": True, "fp64_to_t_end": whole_run(Ws, cs, "fp64", 0.2)}
+        out["c1_sod"] = small_1d_runs(Ws, cs, 0.2, ("fp64", "fp32"))
         Wv, cv = vortex_cfg(1024)
         out["c2_vortex"] = {"1024": per_step(Wv, cv, ("fp64", "fp32", "fp32_mixed"), a.steps, a.warmup)}
         Wv, cv = vortex_cfg(4096)
@@ -466,8 +493,8 @@ def main():
         del Wv
         Wt, ct = bzt_cfg(8192, 1)
         Wb, cb = bzt_cfg(2048, 2)
-        out["c4_bzt"] = {"1d_8192": {"launch_bound": True, **{p + "_to_t_end": whole_run(Wt, ct, p, 0.2)
-                                                              for p in ("fp64", "fp32")}},
+        out["c4_bzt"] = {"1d_8192": {"path": "one launch per step (launch-bound)",
+                                     **{p + "_to_t_end": whole_run(Wt, ct, p, 0.2) for p in ("fp64", "fp32")}},
                          "2d_2048": per_step(Wb, cb, ("fp64", "fp32", "fp32_mixed"), a.steps, a.warmup)}
         out["c4_bzt"]["2d_2048"]["fp32_to_t_end"] = whole_run(Wb, cb, "fp32", 0.2)
         del Wb

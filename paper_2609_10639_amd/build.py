@@ -14,6 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvlbm.so")
 SOURCES = ["vlbm_step2d.hip", "vlbm_step1d.hip", "vlbm_aux.hip", "vlbm_adjoint.hip", "vlbm_adjoint_march.hip",
+           "vlbm_resident1d.hip",
            "vlbm_api.cpp"]
 ARCH = "gfx950"
 

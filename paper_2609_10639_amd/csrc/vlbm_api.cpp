@@ -51,6 +51,7 @@ struct vlbm_ctx {
     int* raw_err = nullptr;
     AdjScratch adj{};
     bool adj_march = false;        // fused single-march adjoint (D2Q4)
+    bool resident = false;         // D1Q2 batches in one resident workgroup (small grids)
     hipStream_t stream;
     int device = 0;                // current device at creation: where the buffers live
     long long n = 0;
@@ -149,11 +150,22 @@ hipError_t launch_one(vlbm_ctx* ctx, long long n, double t_end)
                        : launch_step_d1q2(ctx->kp, s, ctx->prec, fin, fout, ctx->stream);
 }
 
+// steps per launch of the resident D1Q2 kernel: bounds one launch's duration
+// (about 10 ms at 4096 cells) without a measurable cost per launch
+constexpr long long kResidentChunk = 4096;
+
 // launch `count` steps from the host's step index, read back, update the mirror
 vlbm_status run_batch(vlbm_ctx* ctx, long long count, double t_end, long long* executed)
 {
     const long long n0 = ctx->n;
-    for (long long k = 0; k < count; ++k) HIPCHK(ctx, launch_one(ctx, n0 + k, t_end));
+    if (ctx->resident) {
+        for (long long k = 0; k < count; k += kResidentChunk) {
+            KRun r{ctx->ring, ctx->stop_at, ctx->err, n0 + k, std::min(kResidentChunk, count - k), t_end};
+            HIPCHK(ctx, launch_run_d1q2(ctx->kp, r, ctx->prec, ctx->f[0], ctx->f[1], ctx->stream));
+        }
+    } else {
+        for (long long k = 0; k < count; ++k) HIPCHK(ctx, launch_one(ctx, n0 + k, t_end));
+    }
     vlbm_status st = sync_readback(ctx);
     if (st != VLBM_OK) return st;
     const unsigned long long stop = ctx->host_u[0];
@@ -379,6 +391,10 @@ vlbm_status vlbm_create(const vlbm_config* cfg, vlbm_ctx** out)
         vlbm_destroy(ctx);
         return VLBM_ENOMEM;
     }
+    // D1Q2 grids that one workgroup holds run their batches in it (VLBM_D1_RESIDENT=0:
+    // one launch per step, as on larger grids)
+    ctx->resident = cfg->dim == 1 && p.nx <= resident_d1q2_max_cells(ctx->prec);
+    if (const char* env = getenv("VLBM_D1_RESIDENT")) ctx->resident = ctx->resident && atoi(env) != 0;
     if (launch_reset_ctl(ctx->ring, ctx->stop_at, ctx->err, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
         vlbm_destroy(ctx);

@@ -8,6 +8,22 @@ namespace vlbm {
 hipError_t launch_step_d2q4(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st);
 hipError_t launch_step_d1q2(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st);
 int step_d2q4_blocks_per_cu(const KParams& p, int prec);
+
+// A batch of D1Q2 steps in one resident workgroup (vlbm_resident1d.hip), for
+// grids of at most resident_d1q2_max_cells cells: steps n0 .. n0 + count - 1,
+// stopping early at a landing or an inadmissible state (then stop_at = the
+// index of the state reached, and err holds its bits), or not at all when n0 >=
+// stop_at.  State n0 is read from f0 or f1 (n0 & 1), its clock and reductions
+// from ring slot n0 % 3; the state reached goes to buffer n & 1 and ring slot n % 3.
+struct KRun {
+    double* ring;                  // 3 slots of kSlot doubles
+    unsigned long long* stop_at;
+    int* err;
+    long long n0, count;
+    double t_end;                  // landing time (HUGE_VAL: none)
+};
+int resident_d1q2_max_cells(int prec);
+hipError_t launch_run_d1q2(const KParams& p, const KRun& r, int prec, void* f0, void* f1, hipStream_t st);
 // measurement aid: the D2Q4 step's loads and stores without its arithmetic
 hipError_t launch_march_probe(const KParams& p, bool fp32, const void* fin, void* fout, hipStream_t st);
 

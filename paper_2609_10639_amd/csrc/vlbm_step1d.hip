@@ -28,6 +28,9 @@ template <typename ST, typename T, int EOS, int SENSOR, int TILE>
 __global__ void __launch_bounds__(kBlock1) k_step_d1q2(const KParams P, const KStep S, const ST* __restrict__ fin,
                                                        ST* __restrict__ fout)
 {
+    // no fused multiply-adds beyond the ones written out: the resident kernel
+    // (vlbm_resident1d.hip) runs the same arithmetic and so gives the same bits
+#pragma clang fp contract(off)
     constexpr int kSlots1 = TILE + 2 * kHalo1;
     constexpr int NS = (kSlots1 + kBlock1 - 1) / kBlock1;   // slot sets per thread, the last one partial
     static_assert(TILE % kBlock1 == 0, "whole output cells per thread");
