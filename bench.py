@@ -52,8 +52,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "d2q4_fp32_riemann3_4096_traffic.txt")
+# the step kernel, its launch configuration (configure_d2q4, in the same file) and the headers it includes
 KERNEL_SOURCES = ("paper_2609_10639_amd/csrc/vlbm_step2d.hip", "paper_2609_10639_amd/csrc/vlbm_planes.hpp",
-                  "paper_2609_10639_amd/csrc/vlbm_common.hpp", "paper_2609_10639_amd/csrc/vlbm_api.cpp")
+                  "paper_2609_10639_amd/csrc/vlbm_common.hpp")
 WORKLOAD = ("four-quadrant Riemann problem, configuration 3 (interacting shocks), [0,1]^2, outflow, ideal gas "
             "gamma 1.4, D2Q4, Sensor B (0.7, 1, 16), CFL 0.45 retargeted every 4 steps, FP32 populations and arithmetic")
 

@@ -8,6 +8,12 @@ namespace vlbm {
 hipError_t launch_step_d2q4(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st);
 hipError_t launch_step_d1q2(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st);
 int step_d2q4_blocks_per_cu(const KParams& p, int prec);
+// Tiling of the D2Q4 march for a context (strip width, wavefronts per
+// workgroup, rows of loads in flight, segment height; the measured choices
+// with their environment overrides).  Needs dim, nx, ny and retarget_every of p;
+// sets strip_w, nstrips, deep, wpg, ngroups, seg_h and nsegs (one segment of
+// ny rows for D1Q2).
+void configure_d2q4(KParams& p, int prec);
 
 // A batch of D1Q2 steps in one resident workgroup (vlbm_resident1d.hip), for
 // grids of at most resident_d1q2_max_cells cells: steps n0 .. n0 + count - 1,

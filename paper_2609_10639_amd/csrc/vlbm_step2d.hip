@@ -32,6 +32,9 @@
 // Every population is read once from HBM and written once; halo rows and
 // columns are re-read through L2.  S is the storage type of the populations,
 // C the arithmetic type.
+#include <algorithm>
+#include <cstdlib>
+
 #include "vlbm_planes.hpp"
 
 namespace vlbm {
@@ -592,6 +595,79 @@ int step_d2q4_blocks_per_cu(const KParams& p, int prec)
     case PREC_FP32_MIXED: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_d2q4<float, double, 0, 2, 2, false>, bs, l4); break;
     }
     return e == hipSuccess ? nb : 0;
+}
+
+
+// rows per segment of the D2Q4 march: enough wavefronts to fill every CU
+// once at the kernel's occupancy, without a partial second round
+static int choose_seg_h(const KParams& p, int prec)
+{
+    if (const char* env = getenv("VLBM_SEG_H")) {
+        const int v = atoi(env);
+        if (v > 0) return std::min(v, p.ny);
+    }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    int per_cu = step_d2q4_blocks_per_cu(p, prec);
+    if (per_cu <= 0) per_cu = 8 / p.wpg > 0 ? 8 / p.wpg : 1;
+    const long long resident = (long long)cus * per_cu;   // workgroups resident at once
+    long long nsegs = std::max(1LL, resident / p.ngroups);
+    int h = (int)((p.ny + nsegs - 1) / nsegs);
+    // at least 10 rows: shorter segments spend more on their 6 halo rows than
+    // the extra wavefronts win (measured on MI355X at 512^2 and 1024^2, where
+    // 10-11 rows beat 16 by 9-20 % and 8 rows lose again).  FP64 frozen-speed
+    // contexts keep 16: the adjoint rollout replays them beside the FP64 adjoint
+    // march, which then finds free slots (end to end 3.4 -> 3.1 at 1024^2).
+    int hmin = prec == PREC_FP64 && p.retarget_every == 0 ? 16 : 10;
+    if (const char* env = getenv("VLBM_SEG_MIN")) hmin = std::max(1, atoi(env));
+    h = std::max(h, hmin);
+    return std::min(h, p.ny);
+}
+
+void configure_d2q4(KParams& p, int prec)
+{
+    // D2Q4 strips of 56 columns (4 halo lanes a side); measured faster than 48
+    // columns (three whole FP64 lines, but 16 halo lanes), and than 32
+    p.strip_w = 56;
+    if (const char* env = getenv("VLBM_STRIP_W")) {
+        const int v = atoi(env);
+        if (v >= 8 && v <= 56 && v % 2 == 0) p.strip_w = v;   // the step's LDS ring covers halos >= 4
+    }
+    p.nstrips = (p.nx + p.strip_w - 1) / p.strip_w;
+    // FP64 below 1.5M cells: two rows of loads in flight per wavefront at one
+    // wavefront per SIMD, where too few strips x segments exist to fill a second
+    // (measured on MI355X: 512^2 and 1024^2 3-8 % faster; 1280^2 and 1536^2
+    // 1.5 % slower, 2048^2 5 %, 4096^2 14 %).  Not for frozen-speed contexts:
+    // they serve the adjoint rollout, whose replay runs beside the FP64 adjoint
+    // march, and a wavefront holding more than half of a SIMD's registers
+    // (255 VGPRs and 14 AGPRs) cannot share it with one of the march's (248).
+    const long long cells = p.nx * (long long)p.ny;
+    const bool small = cells < (1LL << 22);
+    p.deep = prec == PREC_FP64 && cells < 3 * (1LL << 19) && p.retarget_every != 0;
+    if (const char* env = getenv("VLBM_DEEP")) p.deep = prec == PREC_FP64 && atoi(env) != 0;
+    // adjacent strips per workgroup (measured on MI355X): 2 FP64 wavefronts
+    // (22 KB of LDS ring each), 1 with two rows in flight; with FP32 storage 4
+    // on large grids, where the shared halo lines save HBM traffic, and 1 below
+    // 4M cells, where the march is latency-bound and the per-row barrier costs
+    // more than it saves
+    p.wpg = prec == PREC_FP64 ? (p.deep ? 1 : 2) : (small ? 1 : 4);
+    if (const char* env = getenv("VLBM_WPG")) {
+        const int v = atoi(env);
+        if (v >= 1 && v <= 4) p.wpg = v;
+    }
+    p.wpg = std::min(p.wpg, p.nstrips);
+    p.ngroups = (p.nstrips + p.wpg - 1) / p.wpg;
+    p.seg_h = p.ny;
+    p.nsegs = 1;
+    if (p.dim == 2) {
+        p.seg_h = choose_seg_h(p, prec);
+        p.nsegs = (p.ny + p.seg_h - 1) / p.seg_h;
+    }
+
 }
 
 }  // namespace vlbm
