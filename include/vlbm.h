@@ -191,7 +191,9 @@ size_t vlbm_population_bytes(const vlbm_ctx* ctx);
 vlbm_status vlbm_raw_init(vlbm_ctx* ctx, const double* W0, void* f0, double* norms0);
 
 /* One frozen-speed step f_out = step(f_in) (Eqs. 20-22, 28-35), reading the
- * sensor normalisers from norms_in and writing the norms of f_out. */
+ * sensor normalisers from norms_in and writing the norms of f_out.  f_in and
+ * f_out start on 16-byte boundaries (the D1Q2 step reads and writes 16 bytes
+ * per lane): VLBM_EINVAL otherwise. */
 vlbm_status vlbm_raw_step(vlbm_ctx* ctx, const void* f_in, const double* norms_in, void* f_out,
                           double* norms_out);
 

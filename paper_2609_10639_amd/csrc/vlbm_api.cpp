@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <string>
 
@@ -624,6 +625,7 @@ vlbm_status vlbm_raw_step(vlbm_ctx* ctx, const void* f_in, const double* norms_i
 {
     if (vlbm_status st = need_frozen(ctx)) return st;
     if (!f_in || !f_out || !norms_in || !norms_out) return fail(ctx, VLBM_EINVAL, "null argument");
+    if (((uintptr_t)f_in | (uintptr_t)f_out) & 15) return fail(ctx, VLBM_EINVAL, "populations must be 16-byte aligned");
     HIPCHK(ctx, launch_zero(norms_out, VLBM_NORMS_LEN, ctx->stream));
     KStep s{};
     s.red_in = norms_in;

@@ -30,6 +30,7 @@
 #include <cstdlib>
 
 #include "vlbm_aux.hpp"
+#include "vlbm_d1q2_cell.hpp"
 
 namespace vlbm {
 
@@ -120,8 +121,9 @@ __global__ void __launch_bounds__(NT) k_run_d1q2_resident(const KParams P, const
     // no load waits behind a branch
     const bool self_l = first_edge && cl, self_r = last_edge && ch;
 
-    const Gas<T> g = make_gas<T>(P);
-    const T eoff = (T)P.e_off;
+    D1Consts<T> cs;
+    cs.g = make_gas<T>(P);
+    cs.eoff = (T)P.e_off;
     const int re = P.retarget_every;
     int phase = re > 0 ? (int)(R.n0 % re) : 0;   // n % retarget_every
 
@@ -149,36 +151,16 @@ __global__ void __launch_bounds__(NT) k_run_d1q2_resident(const KParams P, const
             c_new = P.dx / dt;
             last = true;
         }
-        const bool reproj = c_old != c_new;
-        const T r = (T)(c_old / c_new);
-        const T inv2c = (T)(0.5 / c_new);
-        T invM[3];
+        cs.reproj = c_old != c_new;
+        cs.r = (T)(c_old / c_new);
+        cs.inv2c = (T)(0.5 / c_new);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) invM[k] = red[1 + k] > 0.0 ? (T)(1.0 / red[1 + k]) : (T)0;
+        for (int k = 0; k < 3; ++k) cs.invM[k] = red[1 + k] > 0.0 ? (T)(1.0 / red[1 + k]) : (T)0;
 
         // ---- A: reprojection to the new link speed, flux Q(W)
         T fr[K][6], q[K][3];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-#pragma unroll
-            for (int p = 0; p < 6; ++p) fr[j][p] = (T)f[j][p];
-            if (reproj) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const T sm = fr[j][k] + fr[j][3 + k], df = fr[j][k] - fr[j][3 + k];
-                    const T a = (T)0.5 * sm, b = (T)0.5 * r * df;
-                    fr[j][k] = a + b;
-                    fr[j][3 + k] = a - b;
-                }
-            }
-            const T rho = fr[j][0] + fr[j][3], m = fr[j][1] + fr[j][4], E = fr[j][2] + fr[j][5];
-            const T u = m / rho;
-            const T e = E / rho - (T)0.5 * u * u + eoff;
-            const T Pp = eos_pressure<T, EOS>(g, rho, e);
-            q[j][0] = m;
-            q[j][1] = m * u + Pp;
-            q[j][2] = (E + Pp) * u;
-        }
+        for (int j = 0; j < K; ++j) d1_flux<ST, T, EOS>(cs, f[j], fr[j], q[j]);
         // the last owned cell's values (a partial chunk ends before K)
         T qlast[3];
 #pragma unroll
@@ -207,18 +189,13 @@ __global__ void __launch_bounds__(NT) k_run_d1q2_resident(const KParams P, const
             }
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                T acc = 0, j0 = 0;
+                T left[3], right[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    const T left = j == 0 ? ql[k] : q[j - 1 >= 0 ? j - 1 : 0][k];
-                    const T right = (j == nmine - 1 || j == K - 1) ? qr[k] : q[j + 1 < K ? j + 1 : j][k];
-                    T jk = (T)0.5 * (right - left);
-                    if (k == 0) j0 = jk;
-                    if (k == 2) jk = fma(eoff, j0, jk);   // physical energy flux: Q_E,stored + eoff Q_rho
-                    const T sh = jk * invM[k];
-                    acc += sh * sh;
+                    left[k] = j == 0 ? ql[k] : q[j - 1 >= 0 ? j - 1 : 0][k];
+                    right[k] = (j == nmine - 1 || j == K - 1) ? qr[k] : q[j + 1 < K ? j + 1 : j][k];
                 }
-                sv[j] = sqrt(acc / (T)3);
+                sv[j] = d1_activity(cs, left, right);
             }
             slast = sv[K - 1];
 #pragma unroll
@@ -239,23 +216,15 @@ __global__ void __launch_bounds__(NT) k_run_d1q2_resident(const KParams P, const
             }
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                T beta = (T)P.beta_const;
+                T beta;
                 if constexpr (SENSOR != 0) {
                     const T left = j == 0 ? sl : sv[j - 1 >= 0 ? j - 1 : 0];
                     const T right = (j == nmine - 1 || j == K - 1) ? sr : sv[j + 1 < K ? j + 1 : j];
-                    const T sbar = (T)0.25 * left + (T)0.5 * sv[j] + (T)0.25 * right;
-                    T chiv = (T)P.c_sensor * sbar;
-                    chiv = chiv < (T)0 ? (T)0 : (chiv > (T)1 ? (T)1 : chiv);
-                    beta = (T)P.beta_max - (T)(P.beta_max - P.beta_min) * chiv;
+                    beta = d1_beta<T, SENSOR>(P, left, sv[j], right);
+                } else {
+                    beta = d1_beta<T, SENSOR>(P, (T)0, (T)0, (T)0);
                 }
-                const T tb = (T)2 * beta;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const T w2 = (T)0.5 * (fr[j][k] + fr[j][3 + k]);
-                    const T a = q[j][k] * inv2c;
-                    gpc[j][k] = fr[j][k] + tb * ((w2 + a) - fr[j][k]);
-                    gpc[j][3 + k] = fr[j][3 + k] + tb * ((w2 - a) - fr[j][3 + k]);
-                }
+                d1_collide(cs, fr[j], q[j], beta, gpc[j]);
             }
         }
         T glast[6];
@@ -297,23 +266,14 @@ __global__ void __launch_bounds__(NT) k_run_d1q2_resident(const KParams P, const
                 if ((pl && X == 0) || (ph && X == nx - 1)) {   // nx >= 4: distinct cells
                     T pe[3];
                     const int side = X == 0 ? 0 : 1;
-                    pinned_feq<T, EOS>(P, g, side, inv2c, eoff, pe);
+                    pinned_feq<T, EOS>(P, cs.g, side, cs.inv2c, cs.eoff, pe);
 #pragma unroll
                     for (int k = 0; k < 3; ++k) gn[side * 3 + k] = pe[k];
                 }
 #pragma unroll
                 for (int p = 0; p < 6; ++p) f[j][p] = (ST)gn[p];
                 if (j >= nmine) continue;   // past the grid's end (a partial or idle chunk)
-                const T rho = gn[0] + gn[3], m = gn[1] + gn[4], E = gn[2] + gn[5];
-                const T u = m / rho;
-                const T e = E / rho - (T)0.5 * u * u + eoff;
-                const T Pp = eos_pressure<T, EOS>(g, rho, e);
-                const T cs2 = eos_cs2<T, EOS>(g, rho, e);
-                eb |= eos_check<T, EOS>(g, rho, e, cs2);
-                red_s = fmax(red_s, (double)(fabs(u) + sqrt(cs2 > (T)0 ? cs2 : (T)0)));
-                red_M[0] = fmax(red_M[0], (double)fabs(m));
-                red_M[1] = fmax(red_M[1], (double)fabs(m * u + Pp));
-                red_M[2] = fmax(red_M[2], (double)fabs((fma(eoff, rho, E) + Pp) * u));
+                d1_reduce<T, EOS>(cs, gn, red_s, red_M, eb);
             }
         }
         // wave maxima (every lane), then the maximum over the waves from LDS

@@ -1,43 +1,62 @@
 // Fused D1Q2 VLBM time step for gfx950 (arXiv 2609.10639, Sec. III).
 //
-// A 256-thread workgroup processes tiles of consecutive cells (grid-stride over
-// the tiles): 256 cells with FP64 arithmetic, 512 with FP32 arithmetic, whose
-// cells carry half the bytes, so that the fixed cost of a tile (four barriers,
-// the halo) is spread over as many bytes (FP32: +4 %).  At most 1024
-// workgroups with FP64 storage, 4096 with FP32 storage and FP64 arithmetic,
-// 2048 with FP32 (measured best on MI355X).  It stages the
-// cells of a tile plus a 3-cell halo in LDS and runs the step in four
-// barrier-separated phases:
-//   A  load the 6 populations (SoA planes, coalesced), reproject to the new
-//      link speed (Sec. III.E, D = 1 form of Eq. 40), flux Q(W) (Eq. 10);
-//   B  normalised flux-divergence activity s (Eqs. 28-31);
-//   C  box filter, beta (Sensor A, Eq. 34), over-relaxation (Eqs. 20, 22);
-//   D  pull-streaming (Eq. 21), store, and the reductions of the new state.
+// A wavefront updates a tile of consecutive cells.  Each lane holds V cells,
+// V = 16 bytes over the storage size (4 with FP32 storage, 2 with FP64), so
+// that every population plane is read and written with one 16-byte access per
+// lane, and the wavefront's loads of a plane are one contiguous 1 KB stream.
+// The stencil chain of a step (flux, activity, box filter, streaming) reaches
+// 3 cells to each side; HL = ceil(3/V) halo lanes at each end of the
+// wavefront load those cells and repeat their arithmetic, and the other
+// 64 - 2 HL lanes own their cells.  Neighbour values move between lanes by
+// DPP wavefront shifts: no LDS and no barrier.  Workgroups of 4 wavefronts
+// stride over the tiles with the next tile's loads in flight.
+//
+// Per cell, in the order the oracle follows: reprojection to the new link
+// speed and the flux (Eq. 40, Eq. 10), the normalised activity (Eqs. 28-31),
+// beta (Sensor A, Eq. 34, box-filtered), over-relaxation (Eqs. 20, 22),
+// pull-streaming (Eq. 21) with the edge rules, and the reductions of the new
+// state (s_max, M_k) for the next step.  The per-cell arithmetic is shared
+// with the resident kernel (vlbm_d1q2_cell.hpp), so both give the same bits.
+#include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 
-#include "vlbm_common.hpp"
+#include "vlbm_d1q2_cell.hpp"
+#include "vlbm_planes.hpp"
 
 namespace vlbm {
 
-constexpr int kBlock1 = 256;   // threads per workgroup
-constexpr int kHalo1 = 3;
-constexpr int kGrid1 = 1024;   // blocks per launch, FP64 storage (4 per CU); each strides over the tiles
-constexpr int kGrid1F = 4096;  // the same with FP32 storage (16 per CU), for tiles of 256 cells
+constexpr int kBlock1 = 256;   // threads per workgroup: 4 wavefronts, each on its own tiles
+// Workgroups per launch, grid-striding over the tiles (measured on MI355X at
+// 2^26 cells, Sensor A): with FP32 storage 2048 (1024-8192 within 2 %, 16384
+// and more slower: 55 % of 8 TB/s at 2048 against 53 % at 16384 and 47 % at
+// 32768); with FP64 storage 16384 (61 % against 57 % at 2048, 58 % at 32768).
+// A plain copy launched the same ways spreads as widely (56-70 %): how the
+// tiles in flight fall on the HBM channels decides it, not the arithmetic.
+constexpr int kGrid1F = 2048, kGrid1D = 16384;
 
-template <typename ST, typename T, int EOS, int SENSOR, int TILE>
+template <typename ST>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    typedef float T __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec16<double> {
+    typedef double T __attribute__((ext_vector_type(2)));
+};
+
+template <typename ST, typename T, int EOS, int SENSOR>
 __global__ void __launch_bounds__(kBlock1) k_step_d1q2(const KParams P, const KStep S, const ST* __restrict__ fin,
                                                        ST* __restrict__ fout)
 {
     // no fused multiply-adds beyond the ones written out: the resident kernel
     // (vlbm_resident1d.hip) runs the same arithmetic and so gives the same bits
 #pragma clang fp contract(off)
-    constexpr int kSlots1 = TILE + 2 * kHalo1;
-    constexpr int NS = (kSlots1 + kBlock1 - 1) / kBlock1;   // slot sets per thread, the last one partial
-    static_assert(TILE % kBlock1 == 0, "whole output cells per thread");
-    __shared__ T sf[6][kSlots1];   // reprojected populations, plane i*3+k (arithmetic type)
-    __shared__ T sq[3][kSlots1];   // flux Q_k
-    __shared__ T sa[kSlots1];      // activity s
-    __shared__ T sg[6][kSlots1];   // post-collision populations
+    constexpr int V = 16 / (int)sizeof(ST);   // cells per lane
+    constexpr int HL = (3 + V - 1) / V;        // halo lanes at each end
+    constexpr int WO = (64 - 2 * HL) * V;      // cells a tile owns
+    typedef typename Vec16<ST>::T VT;
 
     double c_old, c_new, t, dt;
     bool last;
@@ -45,222 +64,209 @@ __global__ void __launch_bounds__(kBlock1) k_step_d1q2(const KParams P, const KS
     if (blockIdx.x == 0 && threadIdx.x == 0) write_clock(S, t, dt, c_new, last);
     if (blockIdx.x == 0 && threadIdx.x < 64 && !S.frozen) clear_reductions(S, threadIdx.x);
 
-    const Gas<T> g = make_gas<T>(P);
-    const bool reproj = (c_old != c_new);
-    const T r = (T)(c_old / c_new);
-    const T inv2c = (T)(0.5 / c_new);
-    const T eoff = (T)P.e_off;   // energy gauge of the stored populations (physical e = e_stored + eoff)
-    T invM[3];
+    D1Consts<T> cs;
+    cs.g = make_gas<T>(P);
+    cs.eoff = (T)P.e_off;
+    cs.reproj = c_old != c_new;
+    cs.r = (T)(c_old / c_new);
+    cs.inv2c = (T)(0.5 / c_new);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double M = red_fold(S, 1 + k);
-        invM[k] = M > 0.0 ? (T)(1.0 / M) : (T)0;
+        cs.invM[k] = M > 0.0 ? (T)(1.0 / M) : (T)0;
     }
     const int nx = P.nx;
     const long long plane = P.plane;
-    // outflow and pinned edges clamp every neighbour index; a pinned edge then
-    // replaces the population streaming in across it by its ghost's equilibrium
+    // outflow and pinned edges clamp every neighbour to the edge cell itself; a
+    // pinned edge then replaces the population streaming in across it by its
+    // ghost's equilibrium; periodic edges wrap
     const bool cl = P.bc[0] != 0, ch = P.bc[1] != 0;
     const bool pl = P.bc[0] == 2, ph = P.bc[1] == 2;
-    const int ntiles = (nx + TILE - 1) / TILE;
+    const int lane = threadIdx.x & 63;
+    const bool own_lane = lane >= HL && lane < 64 - HL;
+    const int ntiles = (nx + WO - 1) / WO;
+    const int nwaves = (int)gridDim.x * (kBlock1 / 64);
+    const int wave = (int)blockIdx.x * (kBlock1 / 64) + (int)(threadIdx.x >> 6);
 
-    // reductions of the new state over every tile this block visits
     double red_s = 0.0, red_M[3] = {0.0, 0.0, 0.0};
     int errbits = 0;
 
-    // slot s of tile t holds cell X = t TILE - 3 + s; neighbours follow the boundary rule
-    auto cell_of = [&](int X) {
-        if (X < 0) return cl ? 0 : wrap_index(X, nx);
-        if (X >= nx) return ch ? nx - 1 : wrap_index(X, nx);
-        return X;
-    };
-    // Each thread owns slots threadIdx.x + h kBlock1 (h < NS; the last set only
-    // for the first kSlots1 - (NS - 1) kBlock1 threads).  With FP32 storage the
-    // populations of its slots of the next tile are loaded while the current
-    // tile is processed (measured +8 %; with FP64 storage the extra registers
-    // cost more than they hide, -4 %).  The loads are unconditional (past the
-    // last tile the last tile is re-read, in bounds; a thread without a slot in
-    // the last set re-reads its first), so they never merge through copies that
-    // wait at once.
-    constexpr bool kAhead = sizeof(ST) == 4;
-    const bool two = threadIdx.x + (NS - 1) * kBlock1 < kSlots1;   // owns a slot of the last set
-    ST pre[NS][6];
-    auto load_slots = [&](int t) {
+    // The lane's V cells of tile t, plane by plane: one 16-byte load a plane
+    // where they lie inside the grid, else cell by cell through the edge rule
+    // (clamped or wrapped).  Past the last tile the last tile is re-read, in
+    // bounds, so that the prefetch is unconditional.
+    auto load_tile = [&](int tile, ST (&d)[V][6]) {
+        const int X0 = tile * WO - HL * V + lane * V;
+        if (X0 >= 0 && X0 + V <= nx) {
 #pragma unroll
-        for (int h = 0; h < NS; ++h) {
-            const int sl = threadIdx.x + h * kBlock1;
-            const bool full = h < NS - 1;
-            if (full || kAhead || two) {
-                const int c = cell_of(t * TILE - kHalo1 + (full || two ? sl : (int)threadIdx.x));
+            for (int p = 0; p < 6; ++p) {
+                const VT v = *reinterpret_cast<const VT*>(fin + p * plane + X0);
 #pragma unroll
-                for (int j = 0; j < 6; ++j) pre[h][j] = fin[j * plane + c];
+                for (int j = 0; j < V; ++j) d[j][p] = v[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const int X = X0 + j;
+                const int c = X < 0 ? (cl ? 0 : wrap_index(X, nx)) : (X >= nx ? (ch ? nx - 1 : wrap_index(X, nx)) : X);
+#pragma unroll
+                for (int p = 0; p < 6; ++p) d[j][p] = fin[p * plane + c];
             }
         }
     };
-    if (kAhead && (int)blockIdx.x < ntiles) load_slots(blockIdx.x);
 
-    // grid-stride over tiles of TILE cells: few blocks, one set of atomics each
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int x0 = tile * TILE;
-        auto left_of = [&](int s) { return (cl && x0 - kHalo1 + s == 0) ? s : s - 1; };
-        auto right_of = [&](int s) { return (ch && x0 - kHalo1 + s == nx - 1) ? s : s + 1; };
-        if (!kAhead) load_slots(tile);
-        ST cur[NS][6];
+    // the next tile's loads are in flight while a tile is processed (two
+    // tiles ahead measured no faster: the registers cost a wavefront per SIMD)
+    ST nxt[V][6];
+    if (wave < ntiles) load_tile(wave, nxt);
+    for (int tile = wave; tile < ntiles; tile += nwaves) {
+        ST cur[V][6];
 #pragma unroll
-        for (int h = 0; h < NS; ++h)
+        for (int j = 0; j < V; ++j)
 #pragma unroll
-            for (int j = 0; j < 6; ++j) cur[h][j] = pre[h][j];
-        if (kAhead) load_slots(min(tile + (int)gridDim.x, ntiles - 1));
-
-        // ---- A
+            for (int p = 0; p < 6; ++p) cur[j][p] = nxt[j][p];
+        load_tile(min(tile + nwaves, ntiles - 1), nxt);
+        const int X0 = tile * WO - HL * V + lane * V;
+        // a clamped grid edge: the neighbour of the edge cell is the cell itself
+        bool selfL[V], selfR[V];
 #pragma unroll
-        for (int h = 0; h < NS; ++h) {
-            if (h == NS - 1 && !two) break;
-            const int s = threadIdx.x + h * kBlock1;
-            T f[6];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) f[j] = (T)cur[h][j];
-            if (reproj) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const T sm = f[k] + f[3 + k], df = f[k] - f[3 + k];
-                    const T a = (T)0.5 * sm, b = (T)0.5 * r * df;
-                    f[k] = a + b;
-                    f[3 + k] = a - b;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 6; ++j) sf[j][s] = f[j];
-            const T rho = f[0] + f[3], m = f[1] + f[4], E = f[2] + f[5];
-            const T u = m / rho;
-            const T e = E / rho - (T)0.5 * u * u + eoff;
-            const T Pp = eos_pressure<T, EOS>(g, rho, e);
-            sq[0][s] = m;
-            sq[1][s] = m * u + Pp;
-            sq[2][s] = (E + Pp) * u;
+        for (int j = 0; j < V; ++j) {
+            selfL[j] = cl && X0 + j == 0;
+            selfR[j] = ch && X0 + j == nx - 1;
         }
-        __syncthreads();
-        // ---- B
+
+        // ---- reprojection and flux
+        T fr[V][6], q[V][3];
+#pragma unroll
+        for (int j = 0; j < V; ++j) d1_flux<ST, T, EOS>(cs, cur[j], fr[j], q[j]);
+
+        // ---- activity, beta
+        T beta[V];
         if constexpr (SENSOR != 0) {
-            for (int s = threadIdx.x + 1; s < kSlots1 - 1; s += kBlock1) {
-                const int sl = left_of(s), sr = right_of(s);
-                T acc = 0, j0 = 0;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    T jk = (T)0.5 * (sq[k][sr] - sq[k][sl]);
-                    if (k == 0) j0 = jk;
-                    if (k == 2) jk = fma(eoff, j0, jk);   // physical energy flux: Q_E,stored + eoff Q_rho
-                    const T sh = jk * invM[k];
-                    acc += sh * sh;
-                }
-                sa[s] = sqrt(acc / (T)3);
-            }
-            __syncthreads();
-        }
-        // ---- C
-        for (int s = threadIdx.x + 2; s < kSlots1 - 2; s += kBlock1) {
-            T beta = (T)P.beta_const;
-            if constexpr (SENSOR != 0) {
-                const T sbar = (T)0.25 * sa[left_of(s)] + (T)0.5 * sa[s] + (T)0.25 * sa[right_of(s)];
-                T chiv = (T)P.c_sensor * sbar;
-                chiv = chiv < (T)0 ? (T)0 : (chiv > (T)1 ? (T)1 : chiv);
-                beta = (T)P.beta_max - (T)(P.beta_max - P.beta_min) * chiv;
-            }
-            const int X = x0 - kHalo1 + s;
-            if (S.probe) {
-                if (s >= kHalo1 && s < kHalo1 + TILE && X < nx) S.beta_out[X] = (double)beta;
-                continue;
-            }
-            const T tb = (T)2 * beta;
+            T qL[3], qR[3];   // flux of the left lane's last cell and of the right lane's first
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const T w2 = (T)0.5 * (sf[k][s] + sf[3 + k][s]);
-                const T a = sq[k][s] * inv2c;
-                sg[k][s] = sf[k][s] + tb * ((w2 + a) - sf[k][s]);
-                sg[3 + k][s] = sf[3 + k][s] + tb * ((w2 - a) - sf[3 + k][s]);
+                qL[k] = dpp_move<kDppWaveShr1>(q[V - 1][k]);
+                qR[k] = dpp_move<kDppWaveShl1>(q[0][k]);
             }
-        }
-        __syncthreads();
-        // ---- D
+            T sv[V];
 #pragma unroll
-        for (int h = 0; h < TILE / kBlock1; ++h) {
-            if (S.probe) break;
-            const int s = kHalo1 + threadIdx.x + h * kBlock1;
-            const int X = x0 + threadIdx.x + h * kBlock1;
-            if (X < nx) {
-                const int sl = left_of(s), sr = right_of(s);
-                T gn[6];
+            for (int j = 0; j < V; ++j) {
+                T left[3], right[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    gn[k] = sg[k][sl];
-                    gn[3 + k] = sg[3 + k][sr];
+                    left[k] = selfL[j] ? q[j][k] : (j > 0 ? q[j > 0 ? j - 1 : 0][k] : qL[k]);
+                    right[k] = selfR[j] ? q[j][k] : (j < V - 1 ? q[j < V - 1 ? j + 1 : j][k] : qR[k]);
                 }
-                if ((pl && X == 0) || (ph && X == nx - 1)) {   // nx >= 4: distinct cells
-                    T pe[3];
-                    const int side = X == 0 ? 0 : 1;
-                    pinned_feq<T, EOS>(P, g, side, inv2c, eoff, pe);
+                sv[j] = d1_activity(cs, left, right);
+            }
+            const T sL = dpp_move<kDppWaveShr1>(sv[V - 1]), sR = dpp_move<kDppWaveShl1>(sv[0]);
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) gn[side * 3 + k] = pe[k];
+            for (int j = 0; j < V; ++j) {
+                const T left = selfL[j] ? sv[j] : (j > 0 ? sv[j > 0 ? j - 1 : 0] : sL);
+                const T right = selfR[j] ? sv[j] : (j < V - 1 ? sv[j < V - 1 ? j + 1 : j] : sR);
+                beta[j] = d1_beta<T, SENSOR>(P, left, sv[j], right);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) beta[j] = d1_beta<T, SENSOR>(P, (T)0, (T)0, (T)0);
+        }
+        if (S.probe) {   // beta of the current state only
+            if (own_lane)
+#pragma unroll
+                for (int j = 0; j < V; ++j)
+                    if (X0 + j >= 0 && X0 + j < nx) S.beta_out[X0 + j] = (double)beta[j];
+            continue;
+        }
+
+        // ---- over-relaxation
+        T gp[V][6];
+#pragma unroll
+        for (int j = 0; j < V; ++j) d1_collide(cs, fr[j], q[j], beta[j], gp[j]);
+
+        // ---- pull-streaming, edge rules, reductions of the new state, stores
+        T gL[3], gR[3];   // +x populations leaving the left lane's last cell, -x leaving the right lane's first
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            gL[k] = dpp_move<kDppWaveShr1>(gp[V - 1][k]);
+            gR[k] = dpp_move<kDppWaveShl1>(gp[0][3 + k]);
+        }
+        ST out[V][6];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const int X = X0 + j;
+            T gn[6];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                gn[k] = selfL[j] ? gp[j][k] : (j > 0 ? gp[j > 0 ? j - 1 : 0][k] : gL[k]);
+                gn[3 + k] = selfR[j] ? gp[j][3 + k] : (j < V - 1 ? gp[j < V - 1 ? j + 1 : j][3 + k] : gR[k]);
+            }
+            if ((pl && X == 0) || (ph && X == nx - 1)) {   // nx >= 4: distinct cells
+                T pe[3];
+                const int side = X == 0 ? 0 : 1;
+                pinned_feq<T, EOS>(P, cs.g, side, cs.inv2c, cs.eoff, pe);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) gn[side * 3 + k] = pe[k];
+            }
+#pragma unroll
+            for (int p = 0; p < 6; ++p) out[j][p] = (ST)gn[p];
+            if (own_lane && X >= 0 && X < nx) d1_reduce<T, EOS>(cs, gn, red_s, red_M, errbits);
+        }
+        if (own_lane) {
+            if (X0 + V <= nx) {
+#pragma unroll
+                for (int p = 0; p < 6; ++p) {
+                    VT v;
+#pragma unroll
+                    for (int j = 0; j < V; ++j) v[j] = out[j][p];
+                    *reinterpret_cast<VT*>(fout + p * plane + X0) = v;
                 }
+            } else {
 #pragma unroll
-                for (int j = 0; j < 6; ++j) fout[j * plane + X] = (ST)gn[j];
-                const T rho = gn[0] + gn[3], m = gn[1] + gn[4], E = gn[2] + gn[5];
-                const T u = m / rho;
-                const T e = E / rho - (T)0.5 * u * u + eoff;
-                const T Pp = eos_pressure<T, EOS>(g, rho, e);
-                const T cs2 = eos_cs2<T, EOS>(g, rho, e);
-                errbits |= eos_check<T, EOS>(g, rho, e, cs2);
-                red_s = fmax(red_s, (double)(fabs(u) + sqrt(cs2 > (T)0 ? cs2 : (T)0)));
-                red_M[0] = fmax(red_M[0], (double)fabs(m));
-                red_M[1] = fmax(red_M[1], (double)fabs(m * u + Pp));
-                red_M[2] = fmax(red_M[2], (double)fabs((fma(eoff, rho, E) + Pp) * u));
+                for (int j = 0; j < V; ++j)
+                    if (X0 + j < nx)
+#pragma unroll
+                        for (int p = 0; p < 6; ++p) fout[p * plane + X0 + j] = out[j][p];
             }
         }
-        __syncthreads();   // the next tile overwrites sf, sq, sa and sg
     }
     if (!S.probe) block_publish<kBlock1 / 64>(S, red_s, red_M, 3, errbits);
 }
 
-template <typename ST, typename T, int TILE>
-static hipError_t launch_t(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
+template <typename ST, typename T>
+static hipError_t launch_prec(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
 {
-    const int ntiles = (p.nx + TILE - 1) / TILE;
-    int gmax = sizeof(ST) == 4 ? kGrid1F * 256 / TILE : kGrid1;   // FP32 tiles of 512: 2048 blocks
+    constexpr int V = 16 / (int)sizeof(ST), HL = (3 + V - 1) / V, WO = (64 - 2 * HL) * V;
+    const long long ntiles = (p.nx + WO - 1) / WO;
+    long long gmax = sizeof(ST) == 8 ? kGrid1D : kGrid1F;
     if (const char* env = getenv("VLBM_D1_GRID")) {   // tuning override
         const int v = atoi(env);
         if (v >= 64 && v <= 65536) gmax = v;
     }
-    const dim3 grid(ntiles < gmax ? ntiles : gmax), block(kBlock1);
+    const long long blocks = std::min(gmax, (ntiles + kBlock1 / 64 - 1) / (kBlock1 / 64));
+    const dim3 grid((unsigned)blocks), block(kBlock1);
     const ST* in = (const ST*)fin;
     ST* out = (ST*)fout;
-#define VLBM_CASE(E, SN)                                                                            \
-    if (p.eos == E && p.sensor == SN) {                                                             \
-        hipLaunchKernelGGL((k_step_d1q2<ST, T, E, SN, TILE>), grid, block, 0, st, p, s, in, out); \
-        return hipGetLastError();                                                                   \
+#define VLBM_CASE(E, SN)                                                                       \
+    if (p.eos == E && p.sensor == SN) {                                                        \
+        hipLaunchKernelGGL((k_step_d1q2<ST, T, E, SN>), grid, block, 0, st, p, s, in, out); \
+        return hipGetLastError();                                                              \
     }
     VLBM_CASE(0, 0) VLBM_CASE(0, 1) VLBM_CASE(1, 0) VLBM_CASE(1, 1)
 #undef VLBM_CASE
     return hipErrorInvalidValue;
 }
 
-// cells per tile: 512 with FP32 arithmetic, 256 with FP64 (VLBM_D1_TILE overrides, for tuning)
-template <typename ST, typename T>
-static hipError_t launch_tiled(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
-{
-    int tile = sizeof(T) == 4 ? 512 : 256;
-    if (const char* env = getenv("VLBM_D1_TILE")) {
-        const int v = atoi(env);
-        if (v == 256 || v == 512) tile = v;
-    }
-    return tile == 512 ? launch_t<ST, T, 512>(p, s, fin, fout, st) : launch_t<ST, T, 256>(p, s, fin, fout, st);
-}
-
 hipError_t launch_step_d1q2(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st)
 {
+    // the 16-byte accesses need 16-byte aligned planes (a plane holds a
+    // multiple of 64 elements): the library's buffers are, and populations
+    // handed to the raw entry points must be
+    if ((reinterpret_cast<uintptr_t>(fin) | reinterpret_cast<uintptr_t>(fout)) & 15) return hipErrorInvalidValue;
     switch (prec) {
-    case PREC_FP64: return launch_tiled<double, double>(p, s, fin, fout, st);
-    case PREC_FP32: return launch_tiled<float, float>(p, s, fin, fout, st);
-    case PREC_FP32_MIXED: return launch_tiled<float, double>(p, s, fin, fout, st);
+    case PREC_FP64: return launch_prec<double, double>(p, s, fin, fout, st);
+    case PREC_FP32: return launch_prec<float, float>(p, s, fin, fout, st);
+    case PREC_FP32_MIXED: return launch_prec<float, double>(p, s, fin, fout, st);
     }
     return hipErrorInvalidValue;
 }

@@ -220,4 +220,6 @@ def _ptr(t, dtype, numel, what):
         raise ValueError("%s: a contiguous device tensor is needed" % what)
     if t.dtype != dtype or t.numel() != numel:
         raise ValueError("%s: expected %d elements of %s, got %d of %s" % (what, numel, dtype, t.numel(), t.dtype))
+    if t.data_ptr() % 16:
+        raise ValueError("%s: the tensor must start on a 16-byte boundary" % what)
     return ctypes.c_void_p(t.data_ptr())

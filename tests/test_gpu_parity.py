@@ -440,6 +440,30 @@ def test_raw_entry_points_check_their_tensors():
     s.raw_init(W, f, n)
 
 
+def test_raw_step_refuses_misaligned_populations():
+    """The D1Q2 step reads and writes 16 bytes per lane: populations that do
+    not start on a 16-byte boundary are refused by the binding (ValueError)
+    and by the library itself (VLBM_EINVAL), before any kernel runs."""
+    import ctypes
+    import torch
+    from paper_2609_10639_amd import _native as N
+    W0, cfg, _ = sod_case(100)
+    s = _solver(dict(cfg, retarget_every=0, c_fixed=7.0))
+    W = torch.tensor(W0, device="cuda")
+    f, n = s.new_populations(), s.new_norms()
+    s.raw_init(W, f, n)
+    g = s.new_populations()
+    wide = torch.empty(f.numel() + 1, dtype=f.dtype, device="cuda")
+    shifted = wide[1:]   # one element past a 16-byte boundary
+    with pytest.raises(ValueError):
+        s.raw_step(f, n, shifted, s.new_norms())
+    st = N.lib().vlbm_raw_step(s._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(n.data_ptr()),
+                               ctypes.c_void_p(shifted.data_ptr()), ctypes.c_void_p(s.new_norms().data_ptr()))
+    assert st == N.EINVAL
+    s.raw_step(f, n, g, s.new_norms())   # aligned: accepted
+    torch.cuda.synchronize()
+
+
 def test_inadmissible_states_are_reported():
     from paper_2609_10639_amd import _native as N
     W0, cfg, _ = sod_case(200)
