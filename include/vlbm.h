@@ -134,7 +134,15 @@ vlbm_status vlbm_init(vlbm_ctx* ctx, const double* W0, int32_t W0_on_device);
 vlbm_status vlbm_step(vlbm_ctx* ctx, int64_t nsteps, double t_end_cap, int64_t* steps_taken);
 
 /* Advance until t == t_end exactly (Sec. III.E, final-step landing).  No-op if
- * t >= t_end already. */
+ * t >= t_end already.
+ *
+ * Execution of vlbm_step and vlbm_run_to_time: the steps of a call are queued
+ * without host synchronisation and the host reads the clock back once per
+ * batch.  A D1Q2 grid of at most 4096 cells runs each batch of up to 4096 steps
+ * in one workgroup that keeps the populations on chip between steps; the state
+ * after the call, and every later call, is the same bit for bit as with one
+ * launch per step (selected at creation with the environment variable
+ * VLBM_D1_RESIDENT=0, for comparison). */
 vlbm_status vlbm_run_to_time(vlbm_ctx* ctx, double t_end, int64_t* steps_taken);
 
 /* out[dim+2] (host) = sum_x W(x) dx^dim in FP64, by a fixed-order tree
