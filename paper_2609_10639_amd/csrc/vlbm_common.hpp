@@ -182,11 +182,55 @@ __device__ inline void pinned_feq(const KParams& p, const Gas<T>& g, int side, T
     out[NK - 1] = (E - eoff * rho) * inv2d + sgn * ((E + P) * u - eoff * mx) * inv2c;
 }
 
-__device__ __forceinline__ double red_fold(const KStep& s, int j)
+// One step of a wave maximum: v = max(v, v of the lane CTRL names).  Lanes
+// whose source lies outside their 16-lane row keep their own value (DPP
+// bound_ctrl off: the update is skipped and `old`, the lane's own value, is
+// returned), which leaves a maximum unchanged.
+template <int CTRL>
+__device__ __forceinline__ double dpp_max_step(double v)
 {
-    double v = s.red_in[j];
-    for (int i = 1; i < s.red_copies; ++i) v = fmax(v, s.red_in[i * s.red_stride + j]);
-    return v;
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)b, hi = (int)(b >> 32);
+    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+    return fmax(v, __longlong_as_double(((long long)hi2 << 32) | (unsigned int)lo2));
+}
+
+// Maximum over the 64 lanes of a wave, in every lane: row shifts right by 1,
+// 2, 4 and 8 lanes (DPP row_shr, controls 0x111, 0x112, 0x114, 0x118) leave
+// the maximum of each 16-lane row in its last lane; the four rows' maxima are
+// then read from lanes 15, 31, 47 and 63.  Call with the whole wave active.
+__device__ __forceinline__ double wave_max_dpp(double v)
+{
+    v = dpp_max_step<0x111>(v);
+    v = dpp_max_step<0x112>(v);
+    v = dpp_max_step<0x114>(v);
+    v = dpp_max_step<0x118>(v);
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)b, hi = (int)(b >> 32);
+    double m = 0.0;
+#pragma unroll
+    for (int r = 15; r < 64; r += 16) {
+        const int l = __builtin_amdgcn_readlane(lo, r), h = __builtin_amdgcn_readlane(hi, r);
+        m = fmax(m, __longlong_as_double(((long long)h << 32) | (unsigned int)l));
+    }
+    return m;
+}
+
+// The reductions of the current state, fields 0 .. NF-1 (s_max, M_k), each
+// the maximum over the copies: lane i reads copy i (at most 64 copies; the
+// values are non-negative, 0 is neutral) and a wave maximum folds them, one
+// memory latency for all of them.  Call with the whole wave active.
+template <int NF>
+__device__ __forceinline__ void red_fold_wave(const KStep& s, double (&out)[NF])
+{
+    const int lane = threadIdx.x & 63;
+    const int copies = s.red_copies > 1 ? s.red_copies : 1;
+    double v[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) v[j] = lane < copies ? s.red_in[lane * s.red_stride + j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) out[j] = wave_max_dpp(v[j]);
 }
 
 // the copy of the new state's reductions this workgroup publishes into
@@ -204,8 +248,9 @@ __device__ __forceinline__ void clear_reductions(const KStep& s, int lane)
 }
 
 // Clock logic of one step (Sec. III.E): retarget c = s_max/CFL (Eq. 37), dt =
-// dx/c, final-step landing.  Returns false when the step must not run.
-__device__ __forceinline__ bool step_clock(const KParams& p, const KStep& s, double& c_old,
+// dx/c, final-step landing; smax is the current state's s_max (red_fold_wave).
+// Returns false when the step must not run.
+__device__ __forceinline__ bool step_clock(const KParams& p, const KStep& s, double smax, double& c_old,
                                            double& c_new, double& t, double& dt, bool& last)
 {
     last = false;
@@ -215,10 +260,12 @@ __device__ __forceinline__ bool step_clock(const KParams& p, const KStep& s, dou
         c_old = c_new = p.c_fixed;
         return true;
     }
-    if (s.stop_at && (unsigned long long)s.n >= *s.stop_at) return false;
+    // the stop mark and the clock are loaded together (independent reads: one
+    // memory latency, not two in a row), then the stop mark decides
+    const unsigned long long stop = s.stop_at ? *s.stop_at : ~0ull;
     t = s.clock_in[0];
     c_old = s.clock_in[1];
-    const double smax = red_fold(s, 0);
+    if ((unsigned long long)s.n >= stop) return false;
     c_new = c_old;
     if (p.retarget_every > 0 && ((s.n % p.retarget_every) == 0 || smax > c_old)) c_new = smax / p.cfl;
     dt = p.dx / c_new;

@@ -34,41 +34,6 @@
 
 namespace vlbm {
 
-// One step of a wave maximum: v = max(v, v of the lane CTRL names).  Lanes
-// whose source lies outside their 16-lane row keep their own value (DPP
-// bound_ctrl off: the update is skipped and `old`, the lane's own value, is
-// returned), which leaves a maximum unchanged.
-template <int CTRL>
-__device__ __forceinline__ double dpp_max_step(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = (int)b, hi = (int)(b >> 32);
-    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
-    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
-    return fmax(v, __longlong_as_double(((long long)hi2 << 32) | (unsigned int)lo2));
-}
-
-// Maximum over the 64 lanes of a wave, in every lane: row shifts right by 1,
-// 2, 4 and 8 lanes (DPP row_shr, controls 0x111, 0x112, 0x114, 0x118) leave
-// the maximum of each 16-lane row in its last lane; the four rows' maxima are
-// then read from lanes 15, 31, 47 and 63.
-__device__ __forceinline__ double wave_max_dpp(double v)
-{
-    v = dpp_max_step<0x111>(v);
-    v = dpp_max_step<0x112>(v);
-    v = dpp_max_step<0x114>(v);
-    v = dpp_max_step<0x118>(v);
-    const long long b = __double_as_longlong(v);
-    const int lo = (int)b, hi = (int)(b >> 32);
-    double m = 0.0;
-#pragma unroll
-    for (int r = 15; r < 64; r += 16) {
-        const int l = __builtin_amdgcn_readlane(lo, r), h = __builtin_amdgcn_readlane(hi, r);
-        m = fmax(m, __longlong_as_double(((long long)h << 32) | (unsigned int)l));
-    }
-    return m;
-}
-
 template <typename ST, typename T, int EOS, int SENSOR, int K, int NT>
 __global__ void __launch_bounds__(NT) k_run_d1q2_resident(const KParams P, const KRun R, ST* __restrict__ f0,
                                                            ST* __restrict__ f1)
@@ -342,14 +307,17 @@ namespace {
 // precision, same bits from every shape): at 1000 cells 4 cells a lane in 4
 // waves (3.6-3.9 us a step) beat 1 in 16 waves (5.1-6.2) and 8 in 2 (5.3-6.7);
 // at 2000 cells 4 in 8 waves beat 8 in 4; at 4000 cells 8 in 8 waves beat 16
-// in 4 (FP32 7.6 against 9.3 us).  At 8192 cells one CU's arithmetic takes as
-// long as a launch per step on the whole chip (FP32 14.6 against 15.5 us), so
-// larger grids take one launch per step.
+// in 4 (FP32 7.6 against 9.3 us).
+//
+// The resident path is taken where it beats one launch per step (7.5 us a
+// step with FP64 arithmetic, 8.5-9 us in FP32 at these sizes): up to 4096
+// cells in FP32 (4000 cells: 7.6 against 8.8 us), up to 2048 cells with FP64
+// arithmetic, whose 8-cell shape takes 11.2 us at 4000 cells (2000 cells: 6.0
+// against 7.6 us).
 struct ResShape {
     int K, NT;
 };
 constexpr ResShape kShapes[] = {{2, 256}, {4, 256}, {4, 512}, {8, 512}};
-constexpr int kResidentMaxCells = 8 * 512;
 
 bool pick_shape(int nx, ResShape& out)
 {
@@ -394,14 +362,14 @@ hipError_t launch_prec(const KParams& p, const KRun& r, const ResShape& s, void*
 
 int resident_d1q2_max_cells(int prec)
 {
-    (void)prec;
-    return kResidentMaxCells;
+    return prec == PREC_FP32 ? 8 * 512 : 4 * 512;
 }
 
 hipError_t launch_run_d1q2(const KParams& p, const KRun& r, int prec, void* f0, void* f1, hipStream_t st)
 {
     ResShape s;
-    if (p.dim != 1 || p.nx < 4 || !pick_shape(p.nx, s)) return hipErrorInvalidValue;
+    if (p.dim != 1 || p.nx < 4 || p.nx > resident_d1q2_max_cells(prec) || !pick_shape(p.nx, s))
+        return hipErrorInvalidValue;
     switch (prec) {
     case PREC_FP64: return launch_prec<double, double>(p, r, s, f0, f1, st);
     case PREC_FP32: return launch_prec<float, float>(p, r, s, f0, f1, st);

@@ -58,23 +58,6 @@ __global__ void __launch_bounds__(kBlock1) k_step_d1q2(const KParams P, const KS
     constexpr int WO = (64 - 2 * HL) * V;      // cells a tile owns
     typedef typename Vec16<ST>::T VT;
 
-    double c_old, c_new, t, dt;
-    bool last;
-    if (!step_clock(P, S, c_old, c_new, t, dt, last)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) write_clock(S, t, dt, c_new, last);
-    if (blockIdx.x == 0 && threadIdx.x < 64 && !S.frozen) clear_reductions(S, threadIdx.x);
-
-    D1Consts<T> cs;
-    cs.g = make_gas<T>(P);
-    cs.eoff = (T)P.e_off;
-    cs.reproj = c_old != c_new;
-    cs.r = (T)(c_old / c_new);
-    cs.inv2c = (T)(0.5 / c_new);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double M = red_fold(S, 1 + k);
-        cs.invM[k] = M > 0.0 ? (T)(1.0 / M) : (T)0;
-    }
     const int nx = P.nx;
     const long long plane = P.plane;
     // outflow and pinned edges clamp every neighbour to the edge cell itself; a
@@ -119,6 +102,25 @@ __global__ void __launch_bounds__(kBlock1) k_step_d1q2(const KParams P, const KS
     // tiles ahead measured no faster: the registers cost a wavefront per SIMD)
     ST nxt[V][6];
     if (wave < ntiles) load_tile(wave, nxt);
+
+    // the control reads (reductions, clock) after the first tile's loads:
+    // none depends on another, so their memory latencies overlap
+    double R[4];   // s_max, M_k of the current state
+    red_fold_wave<4>(S, R);
+    double c_old, c_new, t, dt;
+    bool last;
+    if (!step_clock(P, S, R[0], c_old, c_new, t, dt, last)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) write_clock(S, t, dt, c_new, last);
+    if (blockIdx.x == 0 && threadIdx.x < 64 && !S.frozen) clear_reductions(S, threadIdx.x);
+
+    D1Consts<T> cs;
+    cs.g = make_gas<T>(P);
+    cs.eoff = (T)P.e_off;
+    cs.reproj = c_old != c_new;
+    cs.r = (T)(c_old / c_new);
+    cs.inv2c = (T)(0.5 / c_new);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) cs.invM[k] = R[1 + k] > 0.0 ? (T)(1.0 / R[1 + k]) : (T)0;
     for (int tile = wave; tile < ntiles; tile += nwaves) {
         ST cur[V][6];
 #pragma unroll

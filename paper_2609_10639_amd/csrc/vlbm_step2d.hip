@@ -371,36 +371,13 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
     const int wave = threadIdx.x >> 6;
     S (*ring)[16][kRingW] = reinterpret_cast<S (*)[16][kRingW]>(vlbm_step_lds) + 3 * wave;
 
-    double c_old, c_new, t, dt;
-    bool last;
-    if (!step_clock(P, St, c_old, c_new, t, dt, last)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) write_clock(St, t, dt, c_new, last);
-    if (blockIdx.x == 0 && threadIdx.x < 64 && !St.frozen) clear_reductions(St, threadIdx.x);
-
-    if (P.bc[0] == 2 || P.bc[1] == 2) {
-        if (threadIdx.x < 2 && P.bc[threadIdx.x] == 2) {
-            C pe[4];
-            pinned_feq<C, EOS>(P, make_gas<C>(P), (int)threadIdx.x, (C)(0.5 / c_new), (C)P.e_off, pe);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) vlbm_pin_lds[4 * threadIdx.x + k] = (double)pe[k];
-        }
-        __syncthreads();
-    }
-
+    // The march's geometry and its first rows' loads come first, then the
+    // reductions of the current state and the clock logic: none depends on
+    // another, so their memory latencies overlap.
     March<S, C, EOS, SENSOR, DEPTH, XPER> m{P, St};
     m.in = make_planes(fin, (unsigned)P.plane);
     m.out = make_planes((const S*)fout, (unsigned)P.plane);
     m.ring = ring;
-    m.g = make_gas<C>(P);
-    // c_old == c_new gives r = 1: the reprojection is then the identity
-    m.r = (C)(c_old / c_new);
-    m.inv2c = (C)(0.5 / c_new);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const double M = red_fold(St, 1 + k);
-        m.invM[k] = M > 0.0 ? (C)(1.0 / M) : (C)0;
-    }
-    m.eoff = (C)P.e_off;
     m.nx = P.nx;
     m.ny = P.ny;
     m.lane = threadIdx.x & 63;
@@ -425,6 +402,36 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
     m.y1 = min(m.y0 + P.seg_h, m.ny);
     m.Rb = m.clo ? max(m.y0 - 3, 0) : m.y0 - 3;
     m.Re = m.chi ? min(m.y1 + 2, m.ny - 1) : m.y1 + 2;
+    if (m.Rb <= m.Re) {
+        m.load_row(m.Rb, m.buf[0]);
+        if constexpr (decltype(m)::DEPTH == 2) m.load_row(min(m.Rb + 1, m.Re), m.buf[1]);
+    }
+
+    double R[5];   // s_max, M_k of the current state
+    red_fold_wave<5>(St, R);
+    double c_old, c_new, t, dt;
+    bool last;
+    if (!step_clock(P, St, R[0], c_old, c_new, t, dt, last)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) write_clock(St, t, dt, c_new, last);
+    if (blockIdx.x == 0 && threadIdx.x < 64 && !St.frozen) clear_reductions(St, threadIdx.x);
+
+    if (P.bc[0] == 2 || P.bc[1] == 2) {
+        if (threadIdx.x < 2 && P.bc[threadIdx.x] == 2) {
+            C pe[4];
+            pinned_feq<C, EOS>(P, make_gas<C>(P), (int)threadIdx.x, (C)(0.5 / c_new), (C)P.e_off, pe);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) vlbm_pin_lds[4 * threadIdx.x + k] = (double)pe[k];
+        }
+        __syncthreads();
+    }
+
+    m.g = make_gas<C>(P);
+    // c_old == c_new gives r = 1: the reprojection is then the identity
+    m.r = (C)(c_old / c_new);
+    m.inv2c = (C)(0.5 / c_new);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m.invM[k] = R[1 + k] > 0.0 ? (C)(1.0 / R[1 + k]) : (C)0;
+    m.eoff = (C)P.e_off;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
         m.Dl[s] = m.Vo[s] = m.Ss[s] = m.Sth[s] = (C)0;
@@ -436,10 +443,6 @@ __global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep 
     m.red_s = (C)0;
     m.ebits = 0;
 
-    if (m.Rb <= m.Re) {
-        m.load_row(m.Rb, m.buf[0]);
-        if constexpr (decltype(m)::DEPTH == 2) m.load_row(min(m.Rb + 1, m.Re), m.buf[1]);
-    }
     const int Rlast = m.y1 + 3;
     // every wavefront of the workgroup runs the same rows (same segment), so the
     // barriers are reached uniformly
