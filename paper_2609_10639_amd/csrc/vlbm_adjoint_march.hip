@@ -399,10 +399,13 @@ __global__ void __launch_bounds__(64) k_adj_march(const KParams P, const S* __re
         for (int v = 0; v < 9; ++v) hring[sl][v][threadIdx.x] = (C)0;
     m.g = make_gas<C>(P);
     m.inv2c = (C)(0.5 / P.c_fixed);
+    // M_k of the state, the maximum over the norms' copies: lane i reads copy
+    // i and a wave maximum folds them (one read per field, not a chain of
+    // dependent reads over the copies)
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double M = norms[1 + k];
-        for (int i = 1; i < kRedCopies; ++i) M = fmax(M, norms[i * kRedStride + 1 + k]);
+        const double M = wave_max_dpp(lane < kRedCopies ? norms[lane * kRedStride + 1 + k] : 0.0);
         m.invM[k] = M > 0.0 ? (C)(1.0 / M) : (C)0;
     }
     m.csen = (C)P.c_sensor;
