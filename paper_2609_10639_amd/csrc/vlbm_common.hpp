@@ -307,14 +307,23 @@ __device__ __forceinline__ int wave_or(int v)
     return v;
 }
 
+// OR of the admissibility bits (ERR_NONHYP | ERR_NONFINITE) over a wave, by
+// two wave-wide votes.  Call with the whole wave active.
+__device__ __forceinline__ int wave_or_errbits(int v)
+{
+    return (__any(v & ERR_NONHYP) ? ERR_NONHYP : 0) | (__any(v & ERR_NONFINITE) ? ERR_NONFINITE : 0);
+}
+
 // Publish the per-lane maxima of one wave: s_max and M_k (nk of them), plus
-// the error bits.  Call with the whole wave active.
+// the error bits.  The maxima fold by DPP (wave_max_dpp), not by a chain of
+// LDS-crossbar shuffles, to keep the end of a launch short.  Call with the
+// whole wave active.
 __device__ __forceinline__ void wave_publish(const KStep& s, double smax, const double* M, int nk, int errbits)
 {
-    smax = wave_max(smax);
+    smax = wave_max_dpp(smax);
     double Mr[4];
-    for (int k = 0; k < nk; ++k) Mr[k] = wave_max(M[k]);
-    errbits = wave_or(errbits);
+    for (int k = 0; k < nk; ++k) Mr[k] = wave_max_dpp(M[k]);
+    errbits = wave_or_errbits(errbits);
     if ((threadIdx.x & 63) == 0) {
         double* out = red_target(s);
         atomic_max_nonneg(&out[0], smax);
@@ -334,10 +343,10 @@ __device__ __forceinline__ void block_publish(const KStep& s, double smax, const
 {
     __shared__ double sh[NW][5];
     __shared__ int she[NW];
-    smax = wave_max(smax);
+    smax = wave_max_dpp(smax);
     double Mr[4] = {0, 0, 0, 0};
-    for (int k = 0; k < nk; ++k) Mr[k] = wave_max(M[k]);
-    errbits = wave_or(errbits);
+    for (int k = 0; k < nk; ++k) Mr[k] = wave_max_dpp(M[k]);
+    errbits = wave_or_errbits(errbits);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         sh[w][0] = smax;
