@@ -483,6 +483,47 @@ __global__ void __launch_bounds__(64) k_adj_march(const KParams P, const S* __re
 // share a maximiser).
 constexpr int kFixThreads = 1024;
 
+// Wave-wide sum and minimum by DPP row shifts (as wave_max_dpp): lanes whose
+// source lies outside their 16-lane row add 0 / keep their own value; the
+// four row results are read from lanes 15, 31, 47 and 63.  Whole wave active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shr(double v, bool zero_fill)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)b, hi = (int)(b >> 32);
+    int lo2, hi2;
+    if (zero_fill) {
+        lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, true);
+        hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, true);
+    } else {
+        lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+        hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+    }
+    return __longlong_as_double(((long long)hi2 << 32) | (unsigned int)lo2);
+}
+__device__ __forceinline__ double row_lane(double v, int r)
+{
+    const long long b = __double_as_longlong(v);
+    const int l = __builtin_amdgcn_readlane((int)b, r), h = __builtin_amdgcn_readlane((int)(b >> 32), r);
+    return __longlong_as_double(((long long)h << 32) | (unsigned int)l);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_shr<0x111>(v, true);
+    v += dpp_shr<0x112>(v, true);
+    v += dpp_shr<0x114>(v, true);
+    v += dpp_shr<0x118>(v, true);
+    return ((row_lane(v, 15) + row_lane(v, 31)) + row_lane(v, 47)) + row_lane(v, 63);
+}
+__device__ __forceinline__ double wave_min_dpp(double v)
+{
+    v = fmin(v, dpp_shr<0x111>(v, false));
+    v = fmin(v, dpp_shr<0x112>(v, false));
+    v = fmin(v, dpp_shr<0x114>(v, false));
+    v = fmin(v, dpp_shr<0x118>(v, false));
+    return fmin(fmin(row_lane(v, 15), row_lane(v, 31)), fmin(row_lane(v, 47), row_lane(v, 63)));
+}
+
 template <typename S, typename C, int EOS>
 __global__ void __launch_bounds__(kFixThreads) k_adjm_fix(KParams p, const S* __restrict__ f,
                                                           const double* __restrict__ rec, int nrec,
@@ -508,16 +549,15 @@ __global__ void __launch_bounds__(kFixThreads) k_adjm_fix(KParams p, const S* __
             }
         }
     }
+    // wave folds by DPP: the sum of dJ/dM_k, the largest |Q| (records with no
+    // cell hold -1), and the first cell holding it
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        for (int o = 32; o > 0; o >>= 1) {
-            a[k] += __shfl_xor(a[k], o, 64);
-            const double v2 = __shfl_xor(v[k], o, 64), i2 = __shfl_xor(ix[k], o, 64);
-            if (v2 > v[k] || (v2 == v[k] && i2 < ix[k])) {
-                v[k] = v2;
-                ix[k] = i2;
-            }
-        }
+    for (int k = 0; k < 4; ++k) {
+        a[k] = wave_sum_dpp(a[k]);
+        const double vm = -wave_min_dpp(-v[k]);
+        ix[k] = wave_min_dpp(v[k] == vm ? ix[k] : HUGE_VAL);
+        v[k] = vm;
+    }
     if (lane == 0)
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
