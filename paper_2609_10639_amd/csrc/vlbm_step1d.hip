@@ -27,13 +27,19 @@
 namespace vlbm {
 
 constexpr int kBlock1 = 256;   // threads per workgroup: 4 wavefronts, each on its own tiles
-// Workgroups per launch, grid-striding over the tiles (measured on MI355X at
-// 2^26 cells, Sensor A): with FP32 storage 2048 (1024-8192 within 2 %, 16384
-// and more slower: 55 % of 8 TB/s at 2048 against 53 % at 16384 and 47 % at
-// 32768); with FP64 storage 16384 (61 % against 57 % at 2048, 58 % at 32768).
-// A plain copy launched the same ways spreads as widely (56-70 %): how the
-// tiles in flight fall on the HBM channels decides it, not the arithmetic.
-constexpr int kGrid1F = 2048, kGrid1D = 16384;
+// Most workgroups per launch, grid-striding over the tiles, every wavefront
+// taking the same number of tiles (measured on MI355X at 2^26 cells, Sensor A,
+// in fractions of 8 TB/s):
+//   FP64 storage, 65536: 68 % (64 % at 16384, 66 % at 32768, 67 % at 131072);
+//   FP32 storage, 32768: 62 % (59 % at 8192, 60 % at 16384, 49 % at 131072,
+//     where each wavefront takes a single tile and nothing is prefetched);
+//   FP32 storage with FP64 arithmetic, 2048: 56 % (56 % at 4096, 55 % at 8192,
+//     49 % at 32768).
+template <typename ST, typename T>
+constexpr long long grid_cap()
+{
+    return sizeof(ST) == 8 ? 65536 : (sizeof(T) == 8 ? 2048 : 32768);
+}
 
 template <typename ST>
 struct Vec16;
@@ -221,7 +227,12 @@ __global__ void __launch_bounds__(kBlock1) k_step_d1q2(const KParams P, const KS
                     VT v;
 #pragma unroll
                     for (int j = 0; j < V; ++j) v[j] = out[j][p];
-                    *reinterpret_cast<VT*>(fout + p * plane + X0) = v;
+                    // FP64 storage: non-temporal stores, 68 % against 66 % of
+                    // 8 TB/s; with FP32 storage they measured 1-2 points slower
+                    if constexpr (sizeof(ST) == 8)
+                        __builtin_nontemporal_store(v, reinterpret_cast<VT*>(fout + p * plane + X0));
+                    else
+                        *reinterpret_cast<VT*>(fout + p * plane + X0) = v;
                 }
             } else {
 #pragma unroll
@@ -240,12 +251,16 @@ static hipError_t launch_prec(const KParams& p, const KStep& s, const void* fin,
 {
     constexpr int V = 16 / (int)sizeof(ST), HL = (3 + V - 1) / V, WO = (64 - 2 * HL) * V;
     const long long ntiles = (p.nx + WO - 1) / WO;
-    long long gmax = sizeof(ST) == 8 ? kGrid1D : kGrid1F;
+    long long gmax = grid_cap<ST, T>();
     if (const char* env = getenv("VLBM_D1_GRID")) {   // tuning override
         const int v = atoi(env);
-        if (v >= 64 && v <= 65536) gmax = v;
+        if (v >= 64 && v <= (1 << 20)) gmax = v;
     }
-    const long long blocks = std::min(gmax, (ntiles + kBlock1 / 64 - 1) / (kBlock1 / 64));
+    // tiles a wavefront takes, then as many workgroups as give every wavefront
+    // that many: no wavefront is left with one tile more than the others
+    const long long need = (ntiles + kBlock1 / 64 - 1) / (kBlock1 / 64);
+    const long long per = (need + gmax - 1) / gmax;
+    const long long blocks = (need + per - 1) / per;
     const dim3 grid((unsigned)blocks), block(kBlock1);
     const ST* in = (const ST*)fin;
     ST* out = (ST*)fout;
