@@ -57,7 +57,9 @@ typedef enum {
     VLBM_ENOMEM = -2,          /* device allocation failed */
     VLBM_EDEVICE = -3,         /* HIP runtime error */
     VLBM_ENONHYPERBOLIC = -4,  /* rho <= 0, c_s^2 <= 0 or 1 - b rho <= 0 (Eq. 14) */
-    VLBM_ENONFINITE = -5       /* NaN or Inf in the state */
+    VLBM_ENONFINITE = -5,      /* NaN or Inf in the state */
+    VLBM_EDONE = 1             /* nothing to do, not an error: t >= t_end already
+                                  (vlbm_run_to_time) or t >= t_end_cap (vlbm_step) */
 } vlbm_status;
 
 /* Boundary kinds.  OUTFLOW: edge-replicated ghost cell (every neighbour index is
@@ -129,12 +131,13 @@ vlbm_status vlbm_init(vlbm_ctx* ctx, const double* W0, int32_t W0_on_device);
 
 /* Advance exactly `nsteps` steps (fewer if t reaches t_end_cap, which then
  * lands exactly; pass INFINITY for no cap).  *steps_taken (nullable) receives
- * the steps executed.  On an EOS failure the state is left at the first
- * inadmissible step and ENONHYPERBOLIC / ENONFINITE is returned. */
+ * the steps executed.  VLBM_EDONE, with no step taken, when t >= t_end_cap
+ * already.  On an EOS failure the state is left at the first inadmissible step
+ * and ENONHYPERBOLIC / ENONFINITE is returned. */
 vlbm_status vlbm_step(vlbm_ctx* ctx, int64_t nsteps, double t_end_cap, int64_t* steps_taken);
 
-/* Advance until t == t_end exactly (Sec. III.E, final-step landing).  No-op if
- * t >= t_end already.
+/* Advance until t == t_end exactly (Sec. III.E, final-step landing).
+ * VLBM_EDONE, with no step taken, if t >= t_end already.
  *
  * Execution of vlbm_step and vlbm_run_to_time: the steps of a call are queued
  * without host synchronisation and the host reads the clock back once per

@@ -9,8 +9,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvlbm.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENONHYPERBOLIC, ENONFINITE = 0, -1, -2, -3, -4, -5
-STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONHYPERBOLIC", -5: "ENONFINITE"}
+OK, EINVAL, ENOMEM, EDEVICE, ENONHYPERBOLIC, ENONFINITE, EDONE = 0, -1, -2, -3, -4, -5, 1
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONHYPERBOLIC", -5: "ENONFINITE",
+                1: "EDONE"}
 BC_PERIODIC, BC_OUTFLOW, BC_PINNED = 0, 1, 2
 EOS_IDEAL, EOS_VDW = 0, 1
 SENSOR_OFF, SENSOR_A, SENSOR_B, SENSOR_AUTO = 0, 1, 2, 3
@@ -106,7 +107,8 @@ def lib():
 
 
 def check(status, handle=None):
-    if status != OK:
+    """Raise VlbmError for an error status; OK and EDONE (nothing to do) pass."""
+    if status not in (OK, EDONE):
         msg = lib().vlbm_last_error(handle).decode() if handle else ""
         raise VlbmError(status, msg)
 

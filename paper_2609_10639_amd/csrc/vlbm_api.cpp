@@ -382,7 +382,8 @@ vlbm_status vlbm_step(vlbm_ctx* ctx, int64_t nsteps, double t_end_cap, int64_t* 
     if (!ctx || nsteps < 0) return fail(ctx, VLBM_EINVAL, "bad argument");
     if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
     if (std::isnan(t_end_cap)) return fail(ctx, VLBM_EINVAL, "t_end_cap is NaN");
-    if (nsteps == 0 || ctx->t >= t_end_cap) return VLBM_OK;
+    if (ctx->t >= t_end_cap) return VLBM_EDONE;
+    if (nsteps == 0) return VLBM_OK;
     HIPCHK(ctx, launch_reset_stop(ctx->stop_at, ctx->err, ctx->stream));
     long long done = 0;
     vlbm_status st = run_batch(ctx, nsteps, std::isinf(t_end_cap) ? HUGE_VAL : t_end_cap, &done);
@@ -395,8 +396,7 @@ vlbm_status vlbm_run_to_time(vlbm_ctx* ctx, double t_end, int64_t* steps_taken)
     if (steps_taken) *steps_taken = 0;
     if (!ctx || !std::isfinite(t_end)) return fail(ctx, VLBM_EINVAL, "bad argument");
     if (!ctx->initialised) return fail(ctx, VLBM_EINVAL, "not initialised");
-    if (ctx->cfg.retarget_every == 0)
-        ; // frozen speed: the landing step still shortens dt
+    if (ctx->t >= t_end) return VLBM_EDONE;
     long long total = 0;
     HIPCHK(ctx, launch_reset_stop(ctx->stop_at, ctx->err, ctx->stream));
     while (ctx->t < t_end) {

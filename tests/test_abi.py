@@ -98,3 +98,14 @@ def test_d2q4_size_cap_boundary(nx, ny, precision, ok):
     assert nx * ny == cap + (0 if ok else 1)
     c = _config(2, nx, ny, precision)
     assert _native.lib().vlbm_check_config(ctypes.byref(c)) == (_native.OK if ok else _native.EINVAL)
+
+
+def test_status_codes_match_the_header():
+    """The binding's status constants are the header's enumerators."""
+    from paper_2609_10639_amd import _native
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef enum \{(.*?)\} vlbm_status;", txt, flags=re.S).group(1)
+    codes = {m.group(1): int(m.group(2)) for m in re.finditer(r"VLBM_(\w+)\s*=\s*(-?\d+)", body)}
+    assert codes == {name: getattr(_native, name) for name in codes}
+    assert codes["EDONE"] > 0 > max(v for k, v in codes.items() if k not in ("OK", "EDONE"))
+    assert set(_native.STATUS_NAMES) == set(codes.values())

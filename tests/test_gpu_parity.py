@@ -393,6 +393,26 @@ def test_save_restore_bitwise():
     assert np.array_equal(s.f(), ref_f) and s.clock() == ref_clock
 
 
+def test_nothing_to_do_returns_edone():
+    """At t_end, vlbm_run_to_time and a capped vlbm_step take no step and
+    return VLBM_EDONE, which the binding passes as success (0 steps)."""
+    import ctypes
+    from paper_2609_10639_amd import _native as N
+    W0, cfg, t_end = sod_case(1000)
+    s = _solver(cfg)
+    s.init(W0)
+    assert s.run_to_time(0.05) > 0
+    clock = s.clock()
+    n = ctypes.c_int64(-1)
+    assert N.lib().vlbm_run_to_time(s._h, 0.05, ctypes.byref(n)) == N.EDONE and n.value == 0
+    assert N.lib().vlbm_run_to_time(s._h, 0.01, ctypes.byref(n)) == N.EDONE and n.value == 0
+    assert N.lib().vlbm_step(s._h, 5, 0.05, ctypes.byref(n)) == N.EDONE and n.value == 0
+    assert N.lib().vlbm_step(s._h, 0, math.inf, ctypes.byref(n)) == N.OK and n.value == 0
+    assert s.run_to_time(0.05) == 0 and s.step(3, t_end_cap=0.05) == 0
+    assert s.clock() == clock
+    assert s.step(2) == 2 and s.clock()[2] == clock[2] + 2
+
+
 def test_restore_refuses_foreign_or_short_checkpoints():
     """A checkpoint carries a header naming its grid, lattice and precision:
     restoring it into another context, or from a buffer shorter than
