@@ -529,7 +529,7 @@ def test_bad_configs_rejected():
     ("vortex1024", "fp64", 4), ("vortex1024", "fp32_mixed", 4), ("vortex1024", "fp32", 4),
     ("riemann4096", "fp32_mixed", 2), ("riemann4096", "fp32", 2), ("riemann4096", "fp64", 2),
     ("bzt2048", "fp64", 3), ("bzt2048", "fp32_mixed", 3), ("bzt2048", "fp32", 3), ("bzt8192", "fp64", 40),
-    ("bzt8192", "fp32", 40), ("sod2p26", "fp64", 3), ("sod2p26", "fp32", 3)])
+    ("bzt8192", "fp32", 40), ("sod2p26", "fp64", 3), ("sod2p26", "fp32", 3), ("sod2p26", "fp32_mixed", 3)])
 def test_full_size_against_oracle(name, precision, steps):
     """At the benchmark sizes and launch configuration: a few steps compared
     with the oracle over the whole grid."""
