@@ -353,6 +353,54 @@ def oracle_sample(n, steps, threads=None):
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
+_ORACLE_RUN = """
+import json, sys, time
+sys.path.insert(0, %r)
+import bench
+from oracle import core
+name = %r
+W0, cfg, t_end = {"c1_sod_1000": lambda: (*bench.sod_cfg(1000), 0.2),
+                  "c4_bzt_tube_8192": lambda: (*bench.bzt_cfg(8192, 1), 0.2),
+                  "c2_vortex_128": lambda: (*bench.vortex_cfg(128), 10.0),
+                  "c2_vortex_256": lambda: (*bench.vortex_cfg(256), 10.0)}[name]()
+o = core.Oracle(**cfg)
+o.init(W0)
+t0 = time.perf_counter()
+steps = o.run_to_time(t_end)
+dt = time.perf_counter() - t0
+print(json.dumps({"seconds": dt, "steps": steps, "cells": cfg["nx"] * cfg["ny"], "t_end": t_end,
+                  "threads": core.threads()}))
+"""
+
+
+def oracle_run(name, threads=None):
+    """A whole oracle run of one of the smaller configurations, in a child
+    process (its OpenMP thread count set there); returns the timing record."""
+    env = dict(os.environ)
+    if threads:
+        env["OMP_NUM_THREADS"] = str(threads)
+    out = subprocess.run([sys.executable, "-c", _ORACLE_RUN % (ROOT, name)], env=env, capture_output=True,
+                         text=True, check=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def oracle_whole_runs():
+    """The FP64 oracle's whole runs of the Sod tube (1000 cells), the dense-gas
+    tube (8192 cells) and the vortex (128^2; 256^2 on all threads only) to
+    their end times, on all host threads and on one."""
+    out = {}
+    for name, one in (("c1_sod_1000", True), ("c4_bzt_tube_8192", True), ("c2_vortex_128", True),
+                      ("c2_vortex_256", False)):
+        rec = {}
+        for label, threads in (("all_threads", None), ("one_thread", 1)) if one else (("all_threads", None),):
+            r = oracle_run(name, threads)
+            rec["steps"], rec["t_end"] = r["steps"], r["t_end"]
+            rec[label] = {"seconds": round(r["seconds"], 3), "threads": r["threads"],
+                          "MLUPS": round(r["cells"] * r["steps"] / r["seconds"] / 1e6, 2)}
+        out[name] = rec
+    return out
+
+
 def cpu_baseline(n, steps_all, steps_one):
     allt = oracle_sample(n, steps_all)
     one = oracle_sample(n, steps_one, threads=1)
@@ -363,6 +411,7 @@ def cpu_baseline(n, steps_all, steps_one):
                 steps_all, n, n, allt["seconds"], allt["threads"]),
             "one_thread": {"value": rate(one), "unit": "MLUPS", "cores": 1,
                            "sample": "%d steps (%.1f s)" % (steps_one, one["seconds"])},
+            "whole_runs": oracle_whole_runs(),
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "build": "gcc -O3 -ffp-contract=off -fopenmp, FP64"}
 
