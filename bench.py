@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--cpu-steps-1t", type=int, default=2, help="oracle steps of the one-thread sample")
     ap.add_argument("--only", default="", help="profiling aid: one measurement, e.g. headline | r12_fp64 | "
                                                 "r3_fp32 | vortex1024_fp32 | bzt2048_fp32 | d1q2_fp32 | "
-                                                "adjoint32 | copy | c1")
+                                                "adjoint32 | copy | c1 | oracle_c2_1024")
     return ap.parse_args()
 
 
@@ -362,25 +362,36 @@ name = %r
 W0, cfg, t_end = {"c1_sod_1000": lambda: (*bench.sod_cfg(1000), 0.2),
                   "c4_bzt_tube_8192": lambda: (*bench.bzt_cfg(8192, 1), 0.2),
                   "c2_vortex_128": lambda: (*bench.vortex_cfg(128), 10.0),
-                  "c2_vortex_256": lambda: (*bench.vortex_cfg(256), 10.0)}[name]()
+                  "c2_vortex_256": lambda: (*bench.vortex_cfg(256), 10.0),
+                  "c2_vortex_1024": lambda: (*bench.vortex_cfg(1024), 10.0)}[name]()
 o = core.Oracle(**cfg)
 o.init(W0)
 t0 = time.perf_counter()
-steps = o.run_to_time(t_end)
+if %r:   # step by step, a progress line every 1000 steps on stderr
+    steps = 0
+    while o.clock()[0] < t_end:
+        o.step(t_end)
+        steps += 1
+        if steps %% 1000 == 0:
+            print("oracle %%s: %%d steps, t = %%.3f, %%.0f s" %% (name, steps, o.clock()[0], time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
+else:
+    steps = o.run_to_time(t_end)
 dt = time.perf_counter() - t0
 print(json.dumps({"seconds": dt, "steps": steps, "cells": cfg["nx"] * cfg["ny"], "t_end": t_end,
                   "threads": core.threads()}))
 """
 
 
-def oracle_run(name, threads=None):
-    """A whole oracle run of one of the smaller configurations, in a child
-    process (its OpenMP thread count set there); returns the timing record."""
+def oracle_run(name, threads=None, progress=False):
+    """A whole oracle run of one configuration, in a child process (its OpenMP
+    thread count set there); returns the timing record.  With `progress` the
+    child reports every 1000 steps on this process's stderr."""
     env = dict(os.environ)
     if threads:
         env["OMP_NUM_THREADS"] = str(threads)
-    out = subprocess.run([sys.executable, "-c", _ORACLE_RUN % (ROOT, name)], env=env, capture_output=True,
-                         text=True, check=True)
+    out = subprocess.run([sys.executable, "-c", _ORACLE_RUN % (ROOT, name, progress)], env=env,
+                         stdout=subprocess.PIPE, stderr=None if progress else subprocess.PIPE, text=True, check=True)
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
@@ -475,6 +486,9 @@ def only(a):
     if o.startswith("march"):
         W0, cfg = riemann_cfg(n, 3)
         return dict(only=o, **march_probe(W0, cfg, "fp32" if o.endswith("32") else "fp64", a.steps, a.warmup))
+    if o == "oracle_c2_1024":   # the oracle's whole vortex run at 1024^2 (minutes of CPU)
+        r = oracle_run("c2_vortex_1024", progress=True)
+        return dict(only=o, **r, MLUPS=round(r["cells"] * r["steps"] / r["seconds"] / 1e6, 2), cpu_model=cpu_model())
     if o == "c1":
         W0, cfg = sod_cfg(1000)
         return dict(only=o, **small_1d_runs(W0, cfg, 0.2, ("fp64", "fp32")))
