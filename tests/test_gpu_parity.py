@@ -127,7 +127,8 @@ def test_bzt_extrusion_fp32_bound():
 
 
 @pytest.mark.parametrize("shape,bc", [((67, 130), (0, 0, 0, 0)), ((67, 130), (1, 1, 1, 1)),
-                                      ((5, 7), (1, 1, 0, 0)), ((61, 4), (0, 0, 1, 1)), ((59, 117), (1, 1, 0, 0))])
+                                      ((5, 7), (1, 1, 0, 0)), ((61, 4), (0, 0, 1, 1)), ((59, 117), (1, 1, 0, 0)),
+                                      ((4, 67), (1, 1, 0, 0)), ((4, 4), (0, 0, 0, 0))])
 def test_ragged_grids_fp64(shape, bc):
     ny, nx = shape
     from paper_2609_10639_amd import problems as pr
