@@ -219,7 +219,8 @@ FP32_STEP_BOUND = {0: 1e-6, 1: 1e-5, 2: 3e-4}
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape,bc,sensor", [((131, 97), (1, 1, 1, 1), 2), ((131, 97), (0, 0, 1, 1), 2),
-                                             ((96, 160), (1, 1, 0, 0), 1), ((70, 70), (0, 0, 0, 0), 0)])
+                                             ((96, 160), (1, 1, 0, 0), 1), ((70, 70), (0, 0, 0, 0), 0),
+                                             ((4, 67), (1, 1, 0, 0), 2), ((5, 7), (0, 0, 0, 0), 2)])
 def test_fused_and_multipass_adjoint_step(precision, shape, bc, sensor, monkeypatch):
     """One adjoint step on ragged grids spanning several strips and segments,
     with every boundary mix: the single-march form and the multi-pass form
