@@ -41,28 +41,19 @@ constexpr long long grid_cap()
     return sizeof(ST) == 8 ? 65536 : (sizeof(T) == 8 ? 2048 : 32768);
 }
 
-template <typename ST>
-struct Vec16;
-template <>
-struct Vec16<float> {
-    typedef float T __attribute__((ext_vector_type(4)));
-};
-template <>
-struct Vec16<double> {
-    typedef double T __attribute__((ext_vector_type(2)));
-};
-
-template <typename ST, typename T, int EOS, int SENSOR>
+// V cells per lane: 16 bytes of each plane (V = 16 / sizeof(ST)), or with FP32
+// storage on grids that leave most of the chip idle 2 cells (8 bytes), which
+// halves each lane's serial arithmetic and doubles the wavefronts.
+template <typename ST, typename T, int EOS, int SENSOR, int V>
 __global__ void __launch_bounds__(kBlock1) k_step_d1q2(const KParams P, const KStep S, const ST* __restrict__ fin,
                                                        ST* __restrict__ fout)
 {
     // no fused multiply-adds beyond the ones written out: the resident kernel
     // (vlbm_resident1d.hip) runs the same arithmetic and so gives the same bits
 #pragma clang fp contract(off)
-    constexpr int V = 16 / (int)sizeof(ST);   // cells per lane
     constexpr int HL = (3 + V - 1) / V;        // halo lanes at each end
     constexpr int WO = (64 - 2 * HL) * V;      // cells a tile owns
-    typedef typename Vec16<ST>::T VT;
+    typedef ST VT __attribute__((ext_vector_type(V)));
 
     const int nx = P.nx;
     const long long plane = P.plane;
@@ -252,10 +243,10 @@ __global__ void __launch_bounds__(kBlock1) k_step_d1q2(const KParams P, const KS
     if (!S.probe) block_publish<kBlock1 / 64>(S, red_s, red_M, 3, errbits);
 }
 
-template <typename ST, typename T>
-static hipError_t launch_prec(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
+template <typename ST, typename T, int V>
+static hipError_t launch_v(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
 {
-    constexpr int V = 16 / (int)sizeof(ST), HL = (3 + V - 1) / V, WO = (64 - 2 * HL) * V;
+    constexpr int HL = (3 + V - 1) / V, WO = (64 - 2 * HL) * V;
     const long long ntiles = (p.nx + WO - 1) / WO;
     long long gmax = grid_cap<ST, T>();
     if (const char* env = getenv("VLBM_D1_GRID")) {   // tuning override
@@ -272,12 +263,41 @@ static hipError_t launch_prec(const KParams& p, const KStep& s, const void* fin,
     ST* out = (ST*)fout;
 #define VLBM_CASE(E, SN)                                                                       \
     if (p.eos == E && p.sensor == SN) {                                                        \
-        hipLaunchKernelGGL((k_step_d1q2<ST, T, E, SN>), grid, block, 0, st, p, s, in, out); \
+        hipLaunchKernelGGL((k_step_d1q2<ST, T, E, SN, V>), grid, block, 0, st, p, s, in, out); \
         return hipGetLastError();                                                              \
     }
     VLBM_CASE(0, 0) VLBM_CASE(0, 1) VLBM_CASE(1, 0) VLBM_CASE(1, 1)
 #undef VLBM_CASE
     return hipErrorInvalidValue;
+}
+
+// Cells per lane: 16 bytes of each plane, except with FP32 storage on grids
+// that need less than the chip's width of 4-cell tiles (248 cells each): there
+// 2 cells a lane, halving each lane's serial arithmetic.  Measured on MI355X,
+// one launch per step:
+//   FP32, below 1024 such tiles (2.5e5 cells): 8192 cells 8.45 -> 7.02 us a
+//     step, 65536 cells 8.58 -> 7.29 us; at 2^19 cells 4 cells a lane are 10 %
+//     faster.
+//   FP32 storage with FP64 arithmetic, whose 4-cell form holds 200-235 VGPRs,
+//     below 65536 such tiles (1.6e7 cells): 8192 cells 8.96 -> 7.36 us, 2^22
+//     cells 59.0 -> 54.5 us; the two are even at 2^24, and at 2^25 4 cells a
+//     lane are 5 % faster.
+// The environment variable VLBM_D1_LANE_CELLS (2 or 4) fixes the choice for
+// FP32 storage.
+template <typename ST, typename T>
+static hipError_t launch_prec(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
+{
+    if constexpr (sizeof(ST) == 8) {
+        return launch_v<ST, T, 2>(p, s, fin, fout, st);
+    } else {
+        const long long tiles4 = (p.nx + 247) / 248;
+        bool two = tiles4 < (sizeof(T) == 8 ? 65536 : 1024);
+        if (const char* env = getenv("VLBM_D1_LANE_CELLS")) {
+            const int v = atoi(env);
+            if (v == 2 || v == 4) two = v == 2;
+        }
+        return two ? launch_v<ST, T, 2>(p, s, fin, fout, st) : launch_v<ST, T, 4>(p, s, fin, fout, st);
+    }
 }
 
 hipError_t launch_step_d1q2(const KParams& p, const KStep& s, int prec, const void* fin, void* fout, hipStream_t st)
