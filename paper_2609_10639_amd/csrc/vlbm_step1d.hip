@@ -1,9 +1,10 @@
 // Fused D1Q2 VLBM time step for gfx950 (arXiv 2609.10639, Sec. III).
 //
-// A wavefront updates a tile of consecutive cells.  Each lane holds V cells,
-// V = 16 bytes over the storage size (4 with FP32 storage, 2 with FP64), so
-// that every population plane is read and written with one 16-byte access per
-// lane, and the wavefront's loads of a plane are one contiguous 1 KB stream.
+// A wavefront updates a tile of consecutive cells.  Each lane holds V cells:
+// on large grids V = 16 bytes over the storage size (4 with FP32 storage, 2
+// with FP64), so that every population plane is read and written with one
+// 16-byte access per lane and the wavefront's loads of a plane are one
+// contiguous 1 KB stream; smaller grids take fewer cells a lane (launch_prec).
 // The stencil chain of a step (flux, activity, box filter, streaming) reaches
 // 3 cells to each side; HL = ceil(3/V) halo lanes at each end of the
 // wavefront load those cells and repeat their arithmetic, and the other
@@ -41,9 +42,7 @@ constexpr long long grid_cap()
     return sizeof(ST) == 8 ? 65536 : (sizeof(T) == 8 ? 2048 : 32768);
 }
 
-// V cells per lane: 16 bytes of each plane (V = 16 / sizeof(ST)), or with FP32
-// storage on grids that leave most of the chip idle 2 cells (8 bytes), which
-// halves each lane's serial arithmetic and doubles the wavefronts.
+// V cells per lane, read and written as one V-element vector access per plane.
 template <typename ST, typename T, int EOS, int SENSOR, int V>
 __global__ void __launch_bounds__(kBlock1) k_step_d1q2(const KParams P, const KStep S, const ST* __restrict__ fin,
                                                        ST* __restrict__ fout)
@@ -271,32 +270,46 @@ static hipError_t launch_v(const KParams& p, const KStep& s, const void* fin, vo
     return hipErrorInvalidValue;
 }
 
-// Cells per lane: 16 bytes of each plane, except with FP32 storage on grids
-// that need less than the chip's width of 4-cell tiles (248 cells each): there
-// 2 cells a lane, halving each lane's serial arithmetic.  Measured on MI355X,
-// one launch per step:
-//   FP32, below 1024 such tiles (2.5e5 cells): 8192 cells 8.45 -> 7.02 us a
-//     step, 65536 cells 8.58 -> 7.29 us; at 2^19 cells 4 cells a lane are 10 %
-//     faster.
-//   FP32 storage with FP64 arithmetic, whose 4-cell form holds 200-235 VGPRs,
-//     below 65536 such tiles (1.6e7 cells): 8192 cells 8.96 -> 7.36 us, 2^22
-//     cells 59.0 -> 54.5 us; the two are even at 2^24, and at 2^25 4 cells a
-//     lane are 5 % faster.
-// The environment variable VLBM_D1_LANE_CELLS (2 or 4) fixes the choice for
-// FP32 storage.
+// Cells per lane (measured on MI355X, one launch per step; every width gives
+// the same bits):
+//   1 cell on grids of at most 2048 one-cell tiles (58 cells each, 1.2e5
+//     cells): the chain of arithmetic each lane runs in series is shortest.
+//     8192 cells: FP64 7.52 -> 6.37 us a step, FP32 7.00 -> 6.20, FP32
+//     storage with FP64 arithmetic 7.39 -> 6.01; 65536 cells 4-7 % faster;
+//     262144 cells 2-8 % slower.
+//   Otherwise 16 bytes of each plane (2 cells with FP64 storage, 4 with FP32),
+//   except with FP32 storage on grids that need less than the chip's width
+//   of 4-cell tiles (248 cells each), where 2 cells halve each lane's work:
+//     FP32 arithmetic below 1024 such tiles (2.5e5 cells; at 2^19 cells 4
+//       cells a lane are 10 % faster);
+//     FP64 arithmetic, whose 4-cell form holds 200-235 VGPRs, below 65536
+//       such tiles (1.6e7 cells: 2^22 cells 59.0 -> 54.5 us; the two are even
+//       at 2^24, and at 2^25 4 cells a lane are 5 % faster).
+// The environment variable VLBM_D1_LANE_CELLS (1, 2, or 4 with FP32 storage)
+// fixes the choice.
+template <typename ST, typename T>
+static int lane_cells(long long nx)
+{
+    int v;
+    if (nx <= 2048LL * 58) v = 1;
+    else if (sizeof(ST) == 8) v = 2;
+    else v = (nx + 247) / 248 < (sizeof(T) == 8 ? 65536 : 1024) ? 2 : 4;
+    if (const char* env = getenv("VLBM_D1_LANE_CELLS")) {
+        const int e = atoi(env);
+        if (e == 1 || e == 2 || (e == 4 && sizeof(ST) == 4)) v = e;
+    }
+    return v;
+}
+
 template <typename ST, typename T>
 static hipError_t launch_prec(const KParams& p, const KStep& s, const void* fin, void* fout, hipStream_t st)
 {
-    if constexpr (sizeof(ST) == 8) {
-        return launch_v<ST, T, 2>(p, s, fin, fout, st);
-    } else {
-        const long long tiles4 = (p.nx + 247) / 248;
-        bool two = tiles4 < (sizeof(T) == 8 ? 65536 : 1024);
-        if (const char* env = getenv("VLBM_D1_LANE_CELLS")) {
-            const int v = atoi(env);
-            if (v == 2 || v == 4) two = v == 2;
-        }
-        return two ? launch_v<ST, T, 2>(p, s, fin, fout, st) : launch_v<ST, T, 4>(p, s, fin, fout, st);
+    switch (lane_cells<ST, T>(p.nx)) {
+    case 1: return launch_v<ST, T, 1>(p, s, fin, fout, st);
+    case 2: return launch_v<ST, T, 2>(p, s, fin, fout, st);
+    default:
+        if constexpr (sizeof(ST) == 4) return launch_v<ST, T, 4>(p, s, fin, fout, st);
+        return hipErrorInvalidValue;
     }
 }
 

@@ -139,22 +139,23 @@ def test_ragged_grids_fp64(shape, bc):
     _check(o, n_o, s, n_g, 0.02, 1e-9, "l1")
 
 
-@pytest.mark.parametrize("precision,path", [("fp64", "resident"), ("fp64", "step"),
-                                            ("fp32", "resident"), ("fp32", "step2"), ("fp32", "step4"),
-                                            ("fp32_mixed", "resident"), ("fp32_mixed", "step2"),
-                                            ("fp32_mixed", "step4")])
-@pytest.mark.parametrize("nx,bc", [(4, (0, 0, 1, 1)), (5, (1, 1, 1, 1)), (7, (0, 0, 1, 1)), (63, (1, 1, 1, 1)),
+@pytest.mark.parametrize("precision,path", [("fp64", "resident"), ("fp64", "step1"), ("fp64", "step2"),
+                                            ("fp32", "resident"), ("fp32", "step1"), ("fp32", "step2"),
+                                            ("fp32", "step4"), ("fp32_mixed", "resident"), ("fp32_mixed", "step1"),
+                                            ("fp32_mixed", "step2"), ("fp32_mixed", "step4")])
+@pytest.mark.parametrize("nx,bc", [(4, (0, 0, 1, 1)), (5, (1, 1, 1, 1)), (7, (0, 0, 1, 1)), (57, (0, 0, 1, 1)),
+                                   (59, (1, 1, 1, 1)), (63, (1, 1, 1, 1)),
                                    (119, (0, 0, 1, 1)), (121, (1, 1, 1, 1)), (241, (0, 0, 1, 1)),
                                    (247, (0, 0, 1, 1)), (249, (1, 1, 1, 1)), (4097, (1, 1, 1, 1))])
 def test_ragged_1d_grids(nx, bc, precision, path, monkeypatch):
     """D1Q2 on the smallest and ragged sizes (one cell fewer or more than the
-    tiles of the per-step kernel: 120 cells with 2 cells a lane, 248 with 4;
-    halo lanes past both grid edges), periodic and outflow edges, with the
-    resident workgroup and with one launch per step at either lane width
+    tiles of the per-step kernel: 58 cells with 1 cell a lane, 120 with 2, 248
+    with 4; halo lanes past both grid edges), periodic and outflow edges, with
+    the resident workgroup and with one launch per step at every lane width
     (4097 cells take the per-step path either way)."""
     from paper_2609_10639_amd import problems as pr
     monkeypatch.setenv("VLBM_D1_RESIDENT", "1" if path == "resident" else "0")
-    if path in ("step2", "step4"):
+    if path in ("step1", "step2", "step4"):
         monkeypatch.setenv("VLBM_D1_LANE_CELLS", path[-1])
     W = pr.random_admissible_state(1, (1, nx), seed=7000 + nx, u_amp=0.3)
     cfg = dict(dim=1, nx=nx, ny=1, dx=1.0 / nx, bc=bc, cfl=0.5, sensor=1, **pr.SENSOR_1D, **pr.IDEAL_AIR.config())
