@@ -141,8 +141,8 @@ vlbm_status vlbm_step(vlbm_ctx* ctx, int64_t nsteps, double t_end_cap, int64_t* 
  *
  * Execution of vlbm_step and vlbm_run_to_time: the steps of a call are queued
  * without host synchronisation and the host reads the clock back once per
- * batch.  A D1Q2 grid of at most 4096 cells in FP32 (2048 with FP64
- * arithmetic) runs each batch of up to 4096 steps in one workgroup that keeps
+ * batch.  A D1Q2 grid of at most 2048 cells runs each batch of up to 4096
+ * steps in one workgroup that keeps
  * the populations on chip between steps; the state
  * after the call, and every later call, is the same bit for bit as with one
  * launch per step (selected at creation with the environment variable

@@ -122,7 +122,7 @@ hipError_t launch_one(vlbm_ctx* ctx, long long n, double t_end)
 }
 
 // steps per launch of the resident D1Q2 kernel: bounds one launch's duration
-// (about 10 ms at 4096 cells) without a measurable cost per launch
+// (about 20 ms at 2048 cells) without a measurable cost per launch
 constexpr long long kResidentChunk = 4096;
 
 // launch `count` steps from the host's step index, read back, update the mirror

@@ -306,18 +306,17 @@ namespace {
 // first that covers the grid.  Measured on MI355X (Sod and BZT tubes, every
 // precision, same bits from every shape): at 1000 cells 4 cells a lane in 4
 // waves (3.6-3.9 us a step) beat 1 in 16 waves (5.1-6.2) and 8 in 2 (5.3-6.7);
-// at 2000 cells 4 in 8 waves beat 8 in 4; at 4000 cells 8 in 8 waves beat 16
-// in 4 (FP32 7.6 against 9.3 us).
+// at 2000 cells 4 in 8 waves beat 8 in 4.
 //
-// The resident path is taken where it beats one launch per step (7.5 us a
-// step with FP64 arithmetic, 8.5-9 us in FP32 at these sizes): up to 4096
-// cells in FP32 (4000 cells: 7.6 against 8.8 us), up to 2048 cells with FP64
-// arithmetic, whose 8-cell shape takes 11.2 us at 4000 cells (2000 cells: 6.0
-// against 7.6 us).
+// The resident path is taken where it beats one launch per step (about 6.1-6.4
+// us a step at these sizes, 1 cell a lane): up to 2048 cells (FP32 5.0 against
+// 6.3 us at 2000 cells, FP64 5.9 against 6.5, FP32 storage with FP64
+// arithmetic even at 6.1).  At 2500-4000 cells 8 cells a lane in 8 waves take
+// 7.4-7.7 us in FP32, and one launch per step is faster.
 struct ResShape {
     int K, NT;
 };
-constexpr ResShape kShapes[] = {{2, 256}, {4, 256}, {4, 512}, {8, 512}};
+constexpr ResShape kShapes[] = {{2, 256}, {4, 256}, {4, 512}};
 
 bool pick_shape(int nx, ResShape& out)
 {
@@ -354,15 +353,14 @@ hipError_t launch_prec(const KParams& p, const KRun& r, const ResShape& s, void*
     if (s.K == 2 && s.NT == 256) return launch_k<ST, T, 2, 256>(p, r, f0, f1, st);
     if (s.K == 4 && s.NT == 256) return launch_k<ST, T, 4, 256>(p, r, f0, f1, st);
     if (s.K == 4 && s.NT == 512) return launch_k<ST, T, 4, 512>(p, r, f0, f1, st);
-    if (s.K == 8 && s.NT == 512) return launch_k<ST, T, 8, 512>(p, r, f0, f1, st);
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int resident_d1q2_max_cells(int prec)
+int resident_d1q2_max_cells(int)
 {
-    return prec == PREC_FP32 ? 8 * 512 : 4 * 512;
+    return 4 * 512;
 }
 
 hipError_t launch_run_d1q2(const KParams& p, const KRun& r, int prec, void* f0, void* f1, hipStream_t st)

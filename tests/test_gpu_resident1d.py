@@ -1,20 +1,20 @@
 """D1Q2 batches in one resident workgroup against one launch per step.
 
-Grids of up to 4096 cells in FP32 and 2048 with FP64 arithmetic run their
-batches of steps in one workgroup that keeps the populations on chip between
-steps (the library's default there);
+Grids of up to 2048 cells run their batches of steps in one workgroup that
+keeps the populations on chip between steps (the library's default there);
 VLBM_D1_RESIDENT=0 at context creation selects one launch per step, the path
 larger grids take.  The two kernels run the same arithmetic in the same order,
 with no fused multiply-add beyond those written out, and reduce the same
 maxima, so they must agree bit for bit: populations, clock (t, c, n), step
 counts, the sensor's beta, and the step and status of an inadmissible state.
-Sizes cover every launch shape (2, 4, 4 and 8 cells a lane in 256, 256, 512
-and 512 threads; the last in FP32 only) at and beside its boundaries, ragged
-chunks included, and the sizes just past each cap.
+Sizes cover every launch shape (2, 4 and 4 cells a lane in 256, 256 and 512
+threads) at and beside its boundaries, ragged chunks included, and sizes past
+the cap (one launch per step in both contexts).
 
 Against the FP64 oracle the resident path is covered by the 1-D parity tests
 at these sizes (Sod at 1000 cells, the dense-gas tube at 1024, the paper's
-shock tubes at 1000 and 2000); the per-step path by those at 5000 and more.
+shock tubes at 1000 and 2000); the per-step path by the ragged-size tests
+(every lane width) and by those above 2048 cells.
 """
 import sys
 
