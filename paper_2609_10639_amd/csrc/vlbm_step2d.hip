@@ -365,7 +365,9 @@ extern __shared__ __align__(16) unsigned char vlbm_step_lds[];
 // neighbouring strips both read are fetched from HBM once and served to the
 // second reader from the caches.
 template <typename S, typename C, int EOS, int SENSOR, int DEPTH, bool XPER>
-__global__ void __launch_bounds__(256) k_step_d2q4(const KParams P, const KStep St, const S* __restrict__ fin,
+// up to 8 wavefronts a workgroup with FP32 storage and arithmetic (512 threads,
+// at most 256 VGPRs a wavefront: the FP32 kernel holds about 145), 4 otherwise
+__global__ void __launch_bounds__(sizeof(S) == 4 && sizeof(C) == 4 ? 512 : 256) k_step_d2q4(const KParams P, const KStep St, const S* __restrict__ fin,
                                                    S* __restrict__ fout)
 {
     const int wave = threadIdx.x >> 6;
@@ -512,7 +514,7 @@ hipError_t launch_step_d2q4(const KParams& p, const KStep& s, int prec, const vo
 // planes into the row below.  It bounds what the step's own access pattern can
 // move through HBM.
 template <typename S>
-__global__ void __launch_bounds__(256) k_march_probe(const KParams P, const S* __restrict__ fin, S* __restrict__ fout)
+__global__ void __launch_bounds__(sizeof(S) == 4 ? 512 : 256) k_march_probe(const KParams P, const S* __restrict__ fin, S* __restrict__ fout)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const Planes in = make_planes(fin, (unsigned)P.plane), out = make_planes((const S*)fout, (unsigned)P.plane);
@@ -656,11 +658,18 @@ void configure_d2q4(KParams& p, int prec)
     // (22 KB of LDS ring each), 1 with two rows in flight; with FP32 storage 4
     // on large grids, where the shared halo lines save HBM traffic, and 1 below
     // 4M cells, where the march is latency-bound and the per-row barrier costs
-    // more than it saves
-    p.wpg = prec == PREC_FP64 ? (p.deep ? 1 : 2) : (small ? 1 : 4);
+    // more than it saves.  FP32 arithmetic from 1e7 cells: 8, one workgroup a
+    // CU (87 KB of LDS) whose eight strips share their halo lines, against
+    // three of 4 (Riemann configuration 3 under Sensor B: 57.6 against 56.1 %
+    // of 8 TB/s at 4096^2, 58.5 / 57.1 % at 3584^2, 58.2 / 56.3 % at 6144^2,
+    // 53.8 / 52.6 % at 2560^2; 2048^2 and 2896^2 0.3 points slower; 6, 10 and
+    // 12 slower at 4096^2).  The FP64 arithmetic of the mixed form loses with
+    // 8 (52.1 against 54.7 %).
+    p.wpg = prec == PREC_FP64 ? (p.deep ? 1 : 2)
+                              : (small ? 1 : (prec == PREC_FP32 && cells >= 10000000LL ? 8 : 4));
     if (const char* env = getenv("VLBM_WPG")) {
         const int v = atoi(env);
-        if (v >= 1 && v <= 4) p.wpg = v;
+        if (v >= 1 && v <= (prec == PREC_FP32 ? 8 : 4)) p.wpg = v;
     }
     p.wpg = std::min(p.wpg, p.nstrips);
     p.ngroups = (p.nstrips + p.wpg - 1) / p.wpg;
