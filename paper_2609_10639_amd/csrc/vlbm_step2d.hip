@@ -658,15 +658,15 @@ void configure_d2q4(KParams& p, int prec)
     // (22 KB of LDS ring each), 1 with two rows in flight; with FP32 storage 4
     // on large grids, where the shared halo lines save HBM traffic, and 1 below
     // 4M cells, where the march is latency-bound and the per-row barrier costs
-    // more than it saves.  FP32 arithmetic from 1e7 cells: 8, one workgroup a
-    // CU (87 KB of LDS) whose eight strips share their halo lines, against
-    // three of 4 (Riemann configuration 3 under Sensor B: 57.6 against 56.1 %
-    // of 8 TB/s at 4096^2, 58.5 / 57.1 % at 3584^2, 58.2 / 56.3 % at 6144^2,
-    // 53.8 / 52.6 % at 2560^2; 2048^2 and 2896^2 0.3 points slower; 6, 10 and
-    // 12 slower at 4096^2).  The FP64 arithmetic of the mixed form loses with
-    // 8 (52.1 against 54.7 %).
-    p.wpg = prec == PREC_FP64 ? (p.deep ? 1 : 2)
-                              : (small ? 1 : (prec == PREC_FP32 && cells >= 10000000LL ? 8 : 4));
+    // more than it saves.  FP32 arithmetic: 8, one workgroup a CU (87 KB of
+    // LDS) whose eight strips share their halo lines, against three of 4, with
+    // the strips narrowed below to spread the columns evenly (Riemann
+    // configuration 3 under Sensor B, fractions of 8 TB/s: 4096^2 58.6 against
+    // 56.1 %, 2896^2 55.0 / 53.8, 2560^2 53.9 / 52.7, 2048^2 47.8 / 45.7; the
+    // dense-gas extrusion at 2048^2 46.1 / 44.8; 5, 6, 10 and 12 slower at
+    // 4096^2).  The FP64 arithmetic of the mixed form loses with 8 (52.1
+    // against 54.7 %).
+    p.wpg = prec == PREC_FP64 ? (p.deep ? 1 : 2) : (small ? 1 : (prec == PREC_FP32 ? 8 : 4));
     if (const char* env = getenv("VLBM_WPG")) {
         const int v = atoi(env);
         if (v >= 1 && v <= (prec == PREC_FP32 ? 8 : 4)) p.wpg = v;
